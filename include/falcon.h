@@ -1,0 +1,109 @@
+/*
+ * falcon.h -- C ABI of the MI355X Falcon codec (lossless compression of
+ * float32 / float64 arrays, arXiv 2511.04140).
+ *
+ * Problem statement followed (Sec. 3, Sec. 4 of the paper): a set V of n
+ * floating-point values is split into chunks of 1025 values; each chunk is
+ * turned into integers (Alg. 2 decimal-place detection and Eq. 3), delta +
+ * zigzag coded (Eq. 4) and written with the adaptive sparse/dense bit-plane
+ * layout (Sec. 3.3, Fig. 9); the variable-length chunks are packed into one
+ * stream by an exclusive prefix sum of their sizes (Sec. 3.4).  Decompression
+ * is the exact inverse (Sec. 4): decompress(compress(x)) reproduces every
+ * bit of x, NaN payloads, infinities, -0.0 and subnormals included.
+ *
+ * Stream format (little-endian):
+ *   bytes  0..31  header: "FLCN", version u8 = 1, dtype u8 (1 = f32,
+ *                 2 = f64), u16 0, chunk length u32 = 1025, u32 0,
+ *                 value count N u64, payload byte count u64
+ *   bytes 32..    one u32 compressed size per chunk (ceil(N / 1025) of them)
+ *   then          the chunk payloads back to back, in chunk order
+ * Each chunk payload: alpha_max u8, beta_hat_max u8, z_1 (8 bytes f64,
+ * 4 bytes f32), bit width w u8, ceil(w/8) scheme-flag bytes, then w rows of
+ * the transposed bit-plane matrix, most significant plane first, each row
+ * dense (128 bytes) or sparse (16-byte bitmap + its non-zero bytes).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     context's device); h_* are host pointers.  The caller owns every
+ *     buffer; the library keeps no caller pointer after the call returns.
+ *   - Input arrays must be aligned to their element size; output streams
+ *     to 4 bytes.
+ *   - Every call is synchronous with respect to the host: it enqueues its
+ *     kernels on `stream` (a hipStream_t; NULL selects the context's own
+ *     stream), waits for them, and only then writes its host outputs.
+ *   - Errors are reported as status codes; nothing unwinds across the ABI.
+ *     On any error the contents of output buffers are unspecified.
+ *   - A context is used by one host thread at a time; distinct contexts are
+ *     independent.
+ */
+#ifndef FALCON_H
+#define FALCON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FALCON_FLOAT32 = 1, FALCON_FLOAT64 = 2 } falcon_dtype;
+
+typedef enum {
+  FALCON_OK = 0,
+  FALCON_ERR_INVALID_ARG = 1,     /* null pointer, bad dtype, misaligned buffer */
+  FALCON_ERR_BUFFER_TOO_SMALL = 2,/* output capacity below what the call needs */
+  FALCON_ERR_CORRUPT_STREAM = 3,  /* stream fails a structural check */
+  FALCON_ERR_DEVICE = 4,          /* a HIP runtime call failed */
+  FALCON_ERR_OUT_OF_MEMORY = 5    /* the context could not grow its scratch */
+} falcon_status;
+
+typedef struct falcon_ctx falcon_ctx;
+
+/* Creates a context on HIP device `device`: a stream, pinned staging and
+ * device scratch (chunk status words for the prefix sum, counters).
+ * Returns FALCON_ERR_DEVICE if the device cannot be used. */
+falcon_status falcon_create(int device, falcon_ctx** out);
+
+/* Releases everything the context owns.  NULL is ignored. */
+void falcon_destroy(falcon_ctx* ctx);
+
+/* Largest stream that compressing n values of type dt can produce:
+ * 32 + ceil(n/1025) * (4 + 8211) for f64, 32 + ceil(n/1025) * (4 + 4107) for
+ * f32 (the all-dense chunk of Sec. 3.3: 11 + 8 + 64 * 128 and
+ * 7 + 4 + 32 * 128 bytes).  Returns 0 for an unknown dtype. */
+size_t falcon_compress_bound(size_t n, falcon_dtype dt);
+
+/* Compresses n values at d_in (device) into d_out (device, out_cap bytes).
+ * Sec. 3.2-3.5 and Alg. 3: per-chunk integer conversion, adaptive bit-plane
+ * encoding, chunk sizes synchronised by a decoupled look-back prefix sum and
+ * chunks written at their offsets.  *out_len (host) receives the stream
+ * length.  Returns FALCON_ERR_BUFFER_TOO_SMALL without launching anything if
+ * out_cap < falcon_compress_bound(n, dt).  n = 0 gives a 32-byte stream. */
+falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt,
+                              void* d_out, size_t out_cap, size_t* out_len, void* stream);
+
+/* Decompresses the stream of in_len bytes at d_in (device) into d_out
+ * (device, out_cap_bytes bytes).  Sec. 4: scan of the size array into chunk
+ * offsets, per-chunk bit-plane decoding, inverse of Eq. 4 and Eq. 3.
+ * *n_out (host) receives the value count N.  The header is checked on the
+ * host (one 32-byte copy); every chunk is checked on the device (bit width,
+ * row extents inside the chunk's size, sizes summing to the payload byte
+ * count): a failure gives FALCON_ERR_CORRUPT_STREAM.  If out_cap_bytes is
+ * below N times the element size, FALCON_ERR_BUFFER_TOO_SMALL is returned
+ * before any launch and *n_out still receives N. */
+falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len, void* d_out,
+                                size_t out_cap_bytes, size_t* n_out, void* stream);
+
+/* Parses a stream header held in host memory (len >= 32 bytes) and returns
+ * the value count and dtype.  FALCON_ERR_CORRUPT_STREAM if the header is not
+ * a version-1 Falcon header. */
+falcon_status falcon_stream_info(const void* h_hdr, size_t len, size_t* n, falcon_dtype* dt);
+
+/* Static, human-readable name of a status code. */
+const char* falcon_status_str(falcon_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FALCON_H */

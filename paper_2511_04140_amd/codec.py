@@ -1,0 +1,164 @@
+"""ctypes binding of libfalcon.so: argument marshalling only.
+
+Every step of compression and decompression runs in the library's HIP
+kernels; nothing here touches the data.  If the library is missing the
+import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libfalcon.so")
+
+FALCON_FLOAT32 = 1
+FALCON_FLOAT64 = 2
+_STATUS = {0: "ok", 1: "invalid argument", 2: "buffer too small", 3: "corrupt stream",
+           4: "device error", 5: "out of memory"}
+ERR_BUFFER_TOO_SMALL = 2
+ERR_CORRUPT_STREAM = 3
+
+
+class FalconError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(lib_path):
+        raise ImportError(
+            f"{lib_path} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(lib_path)
+    vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    L.falcon_create.argtypes = [i, ctypes.POINTER(vp)]
+    L.falcon_create.restype = i
+    L.falcon_destroy.argtypes = [vp]
+    L.falcon_destroy.restype = None
+    L.falcon_compress_bound.argtypes = [sz, i]
+    L.falcon_compress_bound.restype = sz
+    L.falcon_compress.argtypes = [vp, vp, sz, i, vp, sz, ctypes.POINTER(sz), vp]
+    L.falcon_compress.restype = i
+    L.falcon_decompress.argtypes = [vp, vp, sz, vp, sz, ctypes.POINTER(sz), vp]
+    L.falcon_decompress.restype = i
+    L.falcon_stream_info.argtypes = [vp, sz, ctypes.POINTER(sz), ctypes.POINTER(i)]
+    L.falcon_stream_info.restype = i
+    L.falcon_status_str.argtypes = [i]
+    L.falcon_status_str.restype = ctypes.c_char_p
+    return L
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            _lib = _load()
+    return _lib
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float64:
+        return FALCON_FLOAT64
+    if dt == torch.float32:
+        return FALCON_FLOAT32
+    raise TypeError(f"Falcon compresses float32/float64 tensors, got {dt}")
+
+
+def compress_bound(n: int, dtype: torch.dtype) -> int:
+    return lib().falcon_compress_bound(n, _dtype_code(dtype))
+
+
+def _stream_handle(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Codec:
+    """One library context on one GPU (a stream, pinned staging, scratch)."""
+
+    def __init__(self, device: int | torch.device = 0):
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.device = dev
+        self._ctx = ctypes.c_void_p()
+        st = lib().falcon_create(dev.index or 0, ctypes.byref(self._ctx))
+        if st != 0:
+            raise FalconError(st, "falcon_create")
+
+    def close(self):
+        if self._ctx:
+            lib().falcon_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compress(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Compresses a contiguous float32/float64 device tensor; returns the
+        stream as a uint8 device tensor (a view of `out` when given)."""
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("compress needs a contiguous device tensor")
+        code = _dtype_code(x.dtype)
+        n = x.numel()
+        cap = lib().falcon_compress_bound(n, code)
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        olen = ctypes.c_size_t()
+        st = lib().falcon_compress(self._ctx, ctypes.c_void_p(x.data_ptr() if n else 0), n, code,
+                                   ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(olen),
+                                   _stream_handle(x.device))
+        if st != 0:
+            raise FalconError(st, "falcon_compress")
+        return out[: olen.value]
+
+    def decompress(self, stream: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Decompresses a uint8 device tensor holding one stream."""
+        if not stream.is_cuda or stream.dtype != torch.uint8 or not stream.is_contiguous():
+            raise ValueError("decompress needs a contiguous uint8 device tensor")
+        hdr = stream[:32].cpu().numpy() if stream.numel() >= 32 else None
+        if hdr is None:
+            raise FalconError(ERR_CORRUPT_STREAM, "falcon_decompress")
+        n = ctypes.c_size_t()
+        code = ctypes.c_int()
+        st = lib().falcon_stream_info(ctypes.c_void_p(hdr.ctypes.data), 32, ctypes.byref(n), ctypes.byref(code))
+        if st != 0:
+            raise FalconError(st, "falcon_stream_info")
+        dt = torch.float64 if code.value == FALCON_FLOAT64 else torch.float32
+        if out is None:
+            out = torch.empty(n.value, dtype=dt, device=stream.device)
+        nout = ctypes.c_size_t()
+        st = lib().falcon_decompress(self._ctx, ctypes.c_void_p(stream.data_ptr()), stream.numel(),
+                                     ctypes.c_void_p(out.data_ptr() if out.numel() else 0),
+                                     out.numel() * out.element_size(), ctypes.byref(nout),
+                                     _stream_handle(stream.device))
+        if st != 0:
+            raise FalconError(st, "falcon_decompress")
+        return out[: nout.value]
+
+
+_default: dict = {}
+
+
+def _codec_for(device: torch.device) -> Codec:
+    key = device.index or 0
+    if key not in _default:
+        _default[key] = Codec(key)
+    return _default[key]
+
+
+def compress(x: torch.Tensor) -> torch.Tensor:
+    return _codec_for(x.device).compress(x)
+
+
+def decompress(stream: torch.Tensor) -> torch.Tensor:
+    return _codec_for(stream.device).decompress(stream)

@@ -1,0 +1,300 @@
+// codec_device.hpp -- device-side building blocks of the Falcon codec for
+// CDNA4 (gfx950, wave64).
+//
+// Work decomposition: one wavefront owns one chunk of 1025 values (the paper
+// gives one thread a chunk, Sec. 3 / Alg. 3; on CDNA a 64-lane wave keeps the
+// chunk in registers and LDS and moves it with coalesced loads).  Inside a
+// wave two layouts are used:
+//   slot layout        lane L, slot k holds value index 1 + 64k + L
+//                      (k = 0..15); value index 0 (v_1) is held by every
+//                      lane.  Used for the coalesced load and for the
+//                      per-value integer conversion.
+//   contiguous layout  lane L holds entries e_{16L..16L+15} of the delta
+//                      sequence (entry j = z_{j+2}), i.e. the 16 entries
+//                      that make up bytes 2L and 2L+1 of every row of the
+//                      transposed bit-plane matrix.  Used for the bit-plane
+//                      transpose and the row encoding.
+// The switch between the two goes through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace falcon_dev {
+
+constexpr int kChunk = 1025;      // values per chunk (Sec. 5.1.4, n = 64k + 1)
+constexpr int kWaves = 4;         // wavefronts per workgroup
+constexpr int kBlock = 64 * kWaves;
+constexpr int kGSlots = kChunk + 65;         // skewed slots: one pad every 16
+constexpr int kWaveLds = kGSlots * 8;        // 8720 bytes per wave
+constexpr int kHdrBytes = 32;
+
+// fl(10^k): binary64 for k = -22..22, binary32 for k = -10..10, each the
+// value nearest to the exact power (printed by gen_pow10.py).  For
+// 0 <= k <= 22 (binary64) and 0 <= k <= 10 (binary32) the entries are exact
+// (Thm. 3: 5^k fits the significand).
+__constant__ double c_pow10_f64[45] = {
+    0x1.e392010175ee6p-74, 0x1.2e3b40a0e9b4fp-70, 0x1.79ca10c924223p-67, 0x1.d83c94fb6d2acp-64,
+    0x1.2725dd1d243acp-60, 0x1.70ef54646d497p-57, 0x1.cd2b297d889bcp-54, 0x1.203af9ee75616p-50,
+    0x1.6849b86a12b9bp-47, 0x1.c25c268497682p-44, 0x1.19799812dea11p-40, 0x1.5fd7fe1796495p-37,
+    0x1.b7cdfd9d7bdbbp-34, 0x1.12e0be826d695p-30, 0x1.5798ee2308c3ap-27, 0x1.ad7f29abcaf48p-24,
+    0x1.0c6f7a0b5ed8dp-20, 0x1.4f8b588e368f1p-17, 0x1.a36e2eb1c432dp-14, 0x1.0624dd2f1a9fcp-10,
+    0x1.47ae147ae147bp-7, 0x1.999999999999ap-4, 0x1.0000000000000p+0, 0x1.4000000000000p+3,
+    0x1.9000000000000p+6, 0x1.f400000000000p+9, 0x1.3880000000000p+13, 0x1.86a0000000000p+16,
+    0x1.e848000000000p+19, 0x1.312d000000000p+23, 0x1.7d78400000000p+26, 0x1.dcd6500000000p+29,
+    0x1.2a05f20000000p+33, 0x1.74876e8000000p+36, 0x1.d1a94a2000000p+39, 0x1.2309ce5400000p+43,
+    0x1.6bcc41e900000p+46, 0x1.c6bf526340000p+49, 0x1.1c37937e08000p+53, 0x1.6345785d8a000p+56,
+    0x1.bc16d674ec800p+59, 0x1.158e460913d00p+63, 0x1.5af1d78b58c40p+66, 0x1.b1ae4d6e2ef50p+69,
+    0x1.0f0cf064dd592p+73};
+__constant__ float c_pow10_f32[21] = {
+    0x1.b7cdfep-34f, 0x1.12e0bep-30f, 0x1.5798eep-27f, 0x1.ad7f2ap-24f, 0x1.0c6f7ap-20f,
+    0x1.4f8b58p-17f, 0x1.a36e2ep-14f, 0x1.0624dep-10f, 0x1.47ae14p-7f, 0x1.99999ap-4f,
+    0x1.000000p+0f, 0x1.400000p+3f, 0x1.900000p+6f, 0x1.f40000p+9f, 0x1.388000p+13f,
+    0x1.86a000p+16f, 0x1.e84800p+19f, 0x1.312d00p+23f, 0x1.7d7840p+26f, 0x1.dcd650p+29f,
+    0x1.2a05f2p+33f};
+
+// Shared memory of one workgroup: the power tables (copied once per block so
+// that per-lane lookups are LDS reads) and one byte buffer per wavefront.
+struct __attribute__((aligned(16))) BlockLds {
+  double p64[48];
+  float p32[24];
+  uint4 wave[kWaves][kWaveLds / 16];
+};
+
+__device__ __forceinline__ void load_tables(BlockLds& s) {
+  for (int i = threadIdx.x; i < 45; i += blockDim.x) s.p64[i] = c_pow10_f64[i];
+  for (int i = threadIdx.x; i < 21; i += blockDim.x) s.p32[i] = c_pow10_f32[i];
+}
+
+// ---------------------------------------------------------------------------
+// Per-dtype traits.  Constants: alpha <= AMAX keeps 10^alpha exact (Thm. 3),
+// beta <= BMAX is the precision guard (Thm. 2, Thm. 4); the binary32 values
+// (10, 6) follow from the same arguments with a 24-bit significand.
+// ---------------------------------------------------------------------------
+struct TF64 {
+  using F = double;
+  using U = uint64_t;
+  using S = int64_t;
+  static constexpr int W = 64, ZB = 8, AMAX = 22, BMAX = 15, MANT = 52;
+  static constexpr int EXPMAX = 0x7FF, BIAS = 1023;
+  // |v| >= 2^50 > 10^15 means FL10 >= 15 (beta > 15 at alpha = 0);
+  // |v| < 2^-74 < fl(10^-22) means FL10 <= -23 (decimal place > 22).
+  static constexpr int E2_HI = 50, E2_LO = -75;
+  static constexpr int BOUND = 3 + ZB + 8 + 64 * 128;  // 8211
+  static constexpr int POFF = 22;
+  static __device__ __forceinline__ F f(U b) { return __longlong_as_double((long long)b); }
+  static __device__ __forceinline__ U u(F v) { return (U)__double_as_longlong(v); }
+  static __device__ __forceinline__ F mu_scale() { return 0x1p-52; }
+  static __device__ __forceinline__ F rnd(F x) { return __builtin_rint(x); }
+  static __device__ __forceinline__ F abs(F x) { return __builtin_fabs(x); }
+  static __device__ __forceinline__ int expf(U b) { return (int)((b >> MANT) & EXPMAX); }
+  static __device__ __forceinline__ U mag(U b) { return b & 0x7FFFFFFFFFFFFFFFull; }
+  // r is an integer with |r| < 2^51: r + 1.5 * 2^52 is exact and its low
+  // significand bits are r (two's complement offset).
+  static __device__ __forceinline__ S to_int(F r) {
+    F t = r + 6755399441055744.0;
+    return (S)(u(t) - 0x4338000000000000ull);
+  }
+  static __device__ __forceinline__ F pow10(const BlockLds& s, int k) { return s.p64[k + POFF]; }
+};
+
+struct TF32 {
+  using F = float;
+  using U = uint32_t;
+  using S = int32_t;
+  static constexpr int W = 32, ZB = 4, AMAX = 10, BMAX = 6, MANT = 23;
+  static constexpr int EXPMAX = 0xFF, BIAS = 127;
+  // |v| >= 2^20 > 10^6 means FL10 >= 6; |v| < 2^-34 < fl(10^-10) means
+  // FL10 <= -11.
+  static constexpr int E2_HI = 20, E2_LO = -35;
+  static constexpr int BOUND = 3 + ZB + 4 + 32 * 128;  // 4107
+  static constexpr int POFF = 10;
+  static __device__ __forceinline__ F f(U b) { return __uint_as_float(b); }
+  static __device__ __forceinline__ U u(F v) { return __float_as_uint(v); }
+  static __device__ __forceinline__ F mu_scale() { return 0x1p-23f; }
+  static __device__ __forceinline__ F rnd(F x) { return __builtin_rintf(x); }
+  static __device__ __forceinline__ F abs(F x) { return __builtin_fabsf(x); }
+  static __device__ __forceinline__ int expf(U b) { return (int)((b >> MANT) & EXPMAX); }
+  static __device__ __forceinline__ U mag(U b) { return b & 0x7FFFFFFFu; }
+  static __device__ __forceinline__ S to_int(F r) {
+    F t = r + 12582912.0f;  // 1.5 * 2^23, exact for |r| < 2^22
+    return (S)(u(t) - 0x4B400000u);
+  }
+  static __device__ __forceinline__ F pow10(const BlockLds& s, int k) { return s.p32[k + POFF]; }
+};
+
+// Zigzag of Eq. 4: (x << 1) xor (x >> (W-1)), arithmetic shift.
+template <class U>
+__device__ __forceinline__ U zigzag(U x) {
+  using S = typename std::make_signed<U>::type;
+  return (x << 1) ^ (U)((S)x >> (sizeof(U) * 8 - 1));
+}
+template <class U>
+__device__ __forceinline__ U unzigzag(U z) {
+  using S = typename std::make_signed<U>::type;
+  return (z >> 1) ^ (U)(-(S)(z & 1));
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  uint32_t lo = uniform((uint32_t)v), hi = uniform((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int m) {
+  return (uint32_t)__shfl_xor((int)v, m, 64);
+}
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  uint32_t lo = shfl_xor32((uint32_t)v, m), hi = shfl_xor32((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+  uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d, 64);
+  uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += shfl_xor64(v, m);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    uint64_t o = shfl_xor64(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v |= shfl_xor64(v, m);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_or32(uint32_t v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v |= shfl_xor32(v, m);
+  return v;
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+// Inclusive prefix sum over lanes (Hillis-Steele), modulo 2^64.
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t o = shfl_up64(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+// Number of set bits of mask in lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+// Orders this wave's LDS accesses: writes before the barrier are visible to
+// reads of other lanes after it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// 16 x 16 bit-matrix transpose of four (two) independent 16-bit fields per
+// 64-bit (32-bit) word, by recursive block swaps.  Rows are the 16 words of
+// one dword column a[0..15]; afterwards bit i of field q of a[j] is bit j of
+// field q of the original a[i].  The transpose is its own inverse.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void xpose16(uint32_t (&a)[16]) {
+#pragma unroll
+  for (int si = 0; si < 4; ++si) {
+    const int s = 8 >> si;
+    const uint32_t m = si == 0 ? 0x00FF00FFu : si == 1 ? 0x0F0F0F0Fu : si == 2 ? 0x33333333u : 0x55555555u;
+    const uint32_t ms = m << s;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i & s) continue;
+      const uint32_t x = a[i], y = a[i + s];
+      a[i + s] = (y & ~m) | ((x >> s) & m);
+      a[i] = (x & ~ms) | ((y << s) & ms);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back (Sec. 3.4: the compressed chunk sizes are synchronised
+// into offsets; the paper uses a decoupled look-back).  One 64-bit status
+// word per chunk: bits 63..48 launch epoch, 47..46 flag (1 = aggregate, the
+// chunk's own size; 2 = inclusive prefix), 45..0 value.  The epoch lets
+// successive launches reuse the array without clearing it.  The whole wave
+// inspects 64 predecessors at a time.  Returns the exclusive prefix.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kValMask = (1ull << 46) - 1;
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lookback(uint64_t* status, uint64_t t, uint64_t first,
+                                             uint64_t agg, uint32_t epoch, int lane) {
+  const uint64_t tag = (uint64_t)(epoch & 0xFFFF) << 48;
+  if (t == first) {
+    if (lane == 0) status_store(status + t, tag | (2ull << 46) | agg);
+    return 0;
+  }
+  if (lane == 0) status_store(status + t, tag | (1ull << 46) | agg);
+  uint64_t excl = 0;
+  int64_t j = (int64_t)t - 1;
+  while (true) {
+    const int64_t idx = j - lane;
+    const bool valid = idx >= (int64_t)first;
+    const uint64_t s = valid ? status_load(status + idx) : 0;
+    const bool mine = (s >> 48) == (uint64_t)(epoch & 0xFFFF);
+    const uint32_t flag = (uint32_t)(s >> 46) & 3u;
+    const bool ready = !valid || (mine && flag != 0);
+    const bool isp = !valid || (mine && flag == 2);
+    const uint64_t pm = ballot(isp), nm = ballot(!ready);
+    const int firstp = pm ? (int)__builtin_ctzll(pm) : 64;
+    const uint64_t win = firstp >= 63 ? ~0ull : ((2ull << firstp) - 1);
+    if (nm & win) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    const uint64_t contrib = (valid && lane <= firstp) ? (s & kValMask) : 0;
+    excl += wave_sum64(contrib);
+    if (firstp < 64) break;
+    j -= 64;
+  }
+  excl = uniform64(excl);
+  if (lane == 0) status_store(status + t, tag | (2ull << 46) | ((excl + agg) & kValMask));
+  return excl;
+}
+
+// Byte access into a wave's LDS buffer.
+__device__ __forceinline__ uint8_t* wave_bytes(BlockLds& s, int wid) {
+  return reinterpret_cast<uint8_t*>(&s.wave[wid][0]);
+}
+
+}  // namespace falcon_dev

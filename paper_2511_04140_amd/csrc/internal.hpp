@@ -1,0 +1,76 @@
+// internal.hpp -- launch interface between the C ABI (api.cpp) and the
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace falcon_dev {
+
+// Control block of one launch: ticket counter handing out chunks in order,
+// exit counter (the last wave out resets both, so the next launch finds them
+// at zero), and an error word that receives the launch epoch when a chunk
+// fails a check.
+struct Ctl {
+  uint32_t ticket;
+  uint32_t exited;
+  uint32_t error;
+  uint32_t pad;
+};
+
+// One array to compress.  chunk0 is the global index of its first chunk in
+// the launch (prefix of the chunk counts of the series before it).
+struct CompressSeries {
+  const void* in;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t chunk0;
+  uint32_t dtype;  // 1 = f32, 2 = f64
+  uint32_t pad;
+};
+
+struct DecompressSeries {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t chunk0;
+  uint64_t payload_bytes;
+  uint32_t dtype;
+  uint32_t pad;
+};
+
+struct CompressArgs {
+  CompressSeries one;            // used when nseries == 1
+  const CompressSeries* many;    // device array, sorted by chunk0, when nseries > 1
+  uint32_t nseries;
+  uint32_t total_waves;
+  uint64_t total_chunks;
+  uint64_t* status;
+  Ctl* ctl;
+  uint32_t epoch;
+  uint32_t pad;
+};
+
+struct DecompressArgs {
+  DecompressSeries one;
+  const DecompressSeries* many;
+  uint32_t nseries;
+  uint32_t total_waves;
+  uint64_t total_chunks;
+  uint64_t* status;
+  Ctl* ctl;
+  uint32_t epoch;
+  uint32_t pad;
+};
+
+constexpr int kThreadsPerBlock = 256;
+constexpr int kWavesPerBlock = 4;
+
+hipError_t launch_compress(const CompressArgs& a, int grid, hipStream_t s);
+hipError_t launch_decompress(const DecompressArgs& a, int grid, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+// Largest number of co-resident workgroups of each kernel on the device.
+int max_grid_compress(int device);
+int max_grid_decompress(int device);
+
+}  // namespace falcon_dev

@@ -1,0 +1,686 @@
+// kernels.hip -- Falcon compression and decompression kernels for gfx950.
+//
+// Both kernels are persistent: each wavefront repeatedly takes a ticket (the
+// next chunk in stream order) from a device counter, processes the chunk,
+// and exits once the tickets run out.  Tickets make the chunk order match
+// the order in which waves start, which the decoupled look-back needs for
+// forward progress (a chunk only waits for chunks whose owners are already
+// running).
+#include <type_traits>
+
+#include "codec_device.hpp"
+#include "internal.hpp"
+
+namespace falcon_dev {
+
+// ---------------------------------------------------------------------------
+// Alg. 2 building blocks
+// ---------------------------------------------------------------------------
+
+// floor(log10 |v|) of a regular value given its magnitude bits, as the
+// largest k with fl(10^k) <= |v| (the same k as the exponent of the shortest
+// decimal string).  floor(e2 * log10 2) = (e2 * 78913) >> 18 for |e2| < 1700
+// gives k0 with fl(10^k0) <= 2^e2 <= |v| < 2^(e2+1) <= fl(10^(k0+2)), so the
+// answer is k0 or k0 + 1.
+template <class T>
+__device__ __forceinline__ int fl10(const BlockLds& sm, typename T::U mag) {
+  const int e2 = T::expf(mag) - T::BIAS;
+  const int k0 = (e2 * 78913) >> 18;
+  return k0 + (mag >= T::u(T::pow10(sm, k0 + 1)) ? 1 : 0);
+}
+
+// The stopping test of Alg. 2 (Thm. 4): |x - round(x)| <= |x| * 2^-(p-1)
+// with x = v (x) 10^alpha.  Returns the rounded value in r.
+template <class T>
+__device__ __forceinline__ bool eps_test(typename T::U b, typename T::F P, typename T::F& r) {
+  using F = typename T::F;
+  const F x = T::f(b) * P;
+  r = T::rnd(x);
+  return T::abs(x - r) <= T::abs(x) * T::mu_scale();
+}
+
+// Stopping test plus the recover check of Alg. 2: round(v (x) 10^a) / 10^a
+// must give back v bit for bit.
+template <class T>
+__device__ __forceinline__ bool full_test(typename T::U b, typename T::F P) {
+  typename T::F r;
+  const bool ok = eps_test<T>(b, P, r);
+  return ok && T::u(r / P) == b;
+}
+
+// Literal Alg. 2 over the 17 values of this lane (lock-step over alpha).
+// Used only when the fast decision below cannot settle the chunk.  Returns
+// true if some value is an exception; otherwise amax gets the lane's
+// largest decimal place.
+template <class T>
+__device__ bool alg2_literal(const BlockLds& sm, const typename T::U (&vb)[17], int& amax) {
+  uint32_t pend = 0;
+  int lim[17];
+  bool exc = false;
+  amax = 0;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    lim[k] = 0;
+    if (vb[k] != 0) {
+      pend |= 1u << k;
+      const int f = fl10<T>(sm, T::mag(vb[k]));
+      lim[k] = min(T::AMAX, T::BMAX - 1 - f);  // beta = alpha + f + 1 <= BMAX
+    }
+  }
+  for (int a = 0; a <= T::AMAX; ++a) {
+    if (ballot(pend != 0) == 0) break;
+    const typename T::F P = T::pow10(sm, a);
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+      if (pend & (1u << k)) {
+        if (a > lim[k]) {
+          exc = true;
+          pend &= ~(1u << k);
+        } else {
+          typename T::F r;
+          if (eps_test<T>(vb[k], P, r)) {
+            pend &= ~(1u << k);
+            if (T::u(r / P) != vb[k]) exc = true;
+            else amax = max(amax, a);
+          }
+        }
+      }
+    }
+  }
+  if (pend) exc = true;
+  return exc;
+}
+
+// Chunk-level digit transformation decision (Sec. 3.2.3, Alg. 3).  Output:
+// header bytes A (alpha_max) and B (beta_hat_max), and whether Case 1 holds.
+//
+// The paper evaluates Alg. 2 value by value.  Here the wave decides the
+// chunk with the same outcome in fewer steps:
+//  1. A value is an exception outright if it is -0.0, subnormal, Inf or NaN
+//     or has FL10 >= BMAX or FL10 <= -(AMAX+1); with magnitudes ordered as
+//     integers that is |v| < fl(10^-AMAX) or |v| >= fl(10^BMAX) (v != +0).
+//  2. Otherwise let L* = min(AMAX, BMAX-1-FL10(v_max)), the largest scale at
+//     which beta_hat stays within BMAX.  Every value passing the stopping
+//     test and the recover check at L* has alpha_i <= L* (Thm. 2-4: its
+//     shortest string has at most BMAX digits and at most L* places), and
+//     the stopping test holds from alpha_i up to L* and fails below it, so
+//     alpha_max is found by bisection over [0, L*].  The recover check is
+//     repeated at the final alpha_max.
+//  3. A value failing at L* is an exception if L* is its own limit, or if it
+//     fails again at its own limit: a non-exception value passes both tests
+//     at every scale between its decimal place and its limit (the rounding
+//     error of v * 10^s stays within one unit in the last place).
+//  4. Anything else (no exception found, alpha_max > L*, i.e. Case 2 with a
+//     real header) runs the literal Alg. 2.
+template <class T>
+__device__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], int& A, int& B,
+                            bool& case1) {
+  using U = typename T::U;
+  using F = typename T::F;
+  const U mag_lo = T::u(T::pow10(sm, -T::AMAX));
+  const U mag_hi = T::u(T::pow10(sm, T::BMAX));
+  bool exc = false;
+  U vmax = 0;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    const U m = T::mag(vb[k]);
+    exc |= (vb[k] != 0) && (m < mag_lo || m >= mag_hi);
+    vmax = m > vmax ? m : vmax;
+  }
+  if (ballot(exc)) {
+    A = T::AMAX + 1;
+    B = T::BMAX + 1;
+    case1 = false;
+    return;
+  }
+  vmax = (U)uniform64((uint64_t)wave_max64((uint64_t)vmax));
+  if (vmax == 0) {  // every value is +0.0
+    A = 0;
+    B = 0;
+    case1 = true;
+    return;
+  }
+  const int maxfl = (int)uniform((uint32_t)fl10<T>(sm, vmax));
+  const int lstar = min(T::AMAX, T::BMAX - 1 - maxfl);
+  uint32_t fail = 0;
+  {
+    const F P = T::pow10(sm, lstar);
+#pragma unroll
+    for (int k = 0; k < 17; ++k)
+      if (!full_test<T>(vb[k], P)) fail |= 1u << k;
+  }
+  bool literal = false;
+  if (ballot(fail != 0) == 0) {
+    int lo = 0, hi = lstar;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const F P = T::pow10(sm, mid);
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < 17; ++k) {
+        F r;
+        bad |= !eps_test<T>(vb[k], P, r);
+      }
+      if (ballot(bad)) lo = mid + 1;
+      else hi = mid;
+    }
+    if (hi != lstar) {
+      const F P = T::pow10(sm, hi);
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < 17; ++k) bad |= !full_test<T>(vb[k], P);
+      literal = ballot(bad) != 0;
+    }
+    if (!literal) {
+      A = hi;
+      B = hi + maxfl + 1;
+      case1 = true;
+      return;
+    }
+  } else {
+    bool e = false;
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+      if (fail & (1u << k)) {
+        const int f = fl10<T>(sm, T::mag(vb[k]));
+        const int lim = min(T::AMAX, T::BMAX - 1 - f);
+        if (lim == lstar || !full_test<T>(vb[k], T::pow10(sm, lim))) e = true;
+      }
+    }
+    if (ballot(e)) {
+      A = T::AMAX + 1;
+      B = T::BMAX + 1;
+      case1 = false;
+      return;
+    }
+    literal = true;
+  }
+  // literal Alg. 2 for the whole chunk
+  int amax;
+  const bool lexc = alg2_literal<T>(sm, vb, amax);
+  if (ballot(lexc)) {
+    A = T::AMAX + 1;
+    B = T::BMAX + 1;
+    case1 = false;
+    return;
+  }
+  A = wave_max_i32(amax);
+  A = (int)uniform((uint32_t)A);
+  B = A + maxfl + 1;
+  case1 = B <= T::BMAX;
+}
+
+// Field of bit plane p (16 bits: row bytes 2L, 2L+1) after the transpose.
+template <class T, int P>
+__device__ __forceinline__ uint32_t plane_field(const uint32_t (&lo)[16], const uint32_t (&hi)[16]) {
+  if constexpr (P < 32) return (lo[P & 15] >> (16 * ((P >> 4) & 1))) & 0xFFFFu;
+  else return (hi[P & 15] >> (16 * ((P >> 4) & 1))) & 0xFFFFu;
+}
+
+template <int P>
+__device__ __forceinline__ void plane_put(uint32_t (&lo)[16], uint32_t (&hi)[16], uint32_t fld) {
+  if constexpr (P < 32) lo[P & 15] |= fld << (16 * ((P >> 4) & 1));
+  else hi[P & 15] |= fld << (16 * ((P >> 4) & 1));
+}
+
+// Static loop over planes W-1 .. 0.
+template <int P, class Fn>
+__device__ __forceinline__ void for_planes_down(Fn&& fn) {
+  if constexpr (P >= 0) {
+    fn(std::integral_constant<int, P>{});
+    for_planes_down<P - 1>(fn);
+  }
+}
+
+__device__ __forceinline__ void write_stream_header(uint8_t* out, uint32_t dtype, uint64_t n,
+                                                    uint64_t payload, int lane) {
+  if (lane < 8) {
+    uint32_t w;
+    switch (lane) {
+      case 0: w = 0x4E434C46u; break;       // "FLCN"
+      case 1: w = 1u | (dtype << 8); break; // version 1, dtype, u16 0
+      case 2: w = (uint32_t)kChunk; break;
+      case 3: w = 0; break;
+      case 4: w = (uint32_t)n; break;
+      case 5: w = (uint32_t)(n >> 32); break;
+      case 6: w = (uint32_t)payload; break;
+      default: w = (uint32_t)(payload >> 32); break;
+    }
+    reinterpret_cast<uint32_t*>(out)[lane] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compression of one chunk (Alg. 3 for one chunk, executed by one wave)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressSeries& sd, uint64_t c,
+                               uint64_t nc, uint64_t tglob, uint64_t* status, uint32_t epoch, int lane) {
+  using U = typename T::U;
+  using F = typename T::F;
+  const U* in = reinterpret_cast<const U*>(sd.in);
+  const uint64_t base = c * kChunk;
+  const uint64_t rem = sd.n - base;
+  const uint32_t nv = rem < (uint64_t)kChunk ? (uint32_t)rem : (uint32_t)kChunk;
+
+  // a1: coalesced load, slot layout; positions past the end repeat the last
+  // value (padding of a partial last chunk).
+  U vb[17];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    uint32_t idx = 1 + 64 * k + lane;
+    idx = idx < nv ? idx : nv - 1;
+    vb[k] = __builtin_nontemporal_load(in + base + idx);
+  }
+  vb[16] = in[base];
+
+  // a2-a3: decimal places and the chunk case
+  int A, B;
+  bool case1;
+  decide_case<T>(sm, vb, A, B, case1);
+
+  // a4: Eq. 3 -> g, written to LDS in skewed natural order
+  U* g = reinterpret_cast<U*>(buf);
+  {
+    const F P = T::pow10(sm, case1 ? A : 0);
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+      U gk;
+      if (case1) {
+        F r;
+        eps_test<T>(vb[k], P, r);
+        gk = (U)T::to_int(r);
+      } else {
+        gk = zigzag<U>(vb[k]);
+      }
+      if (k < 16) {
+        const uint32_t i = 1 + 64 * k + lane;
+        g[i + (i >> 4)] = gk;
+      } else if (lane == 0) {
+        g[0] = gk;
+      }
+    }
+  }
+  wave_lds_sync();
+
+  // a5: Eq. 4 in the contiguous layout: e[t] = z_{16L+t+2}
+  U e[16];
+  U z1;
+  {
+    const uint32_t b0 = 17u * lane;
+    U prev = g[b0];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const U cur = g[b0 + 1 + t + (t == 15 ? 1 : 0)];
+      e[t] = zigzag<U>((U)(cur - prev));
+      prev = cur;
+    }
+    z1 = g[0];
+  }
+  wave_lds_sync();
+
+  // a6: bit width w = W - min lead over z_2..z_n (lead of 0 is W)
+  U orv = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) orv |= e[t];
+  uint32_t w;
+  if constexpr (sizeof(U) == 8) {
+    const uint64_t o = uniform64(wave_or64((uint64_t)orv));
+    w = o ? 64u - (uint32_t)__builtin_clzll(o) : 0u;
+  } else {
+    const uint32_t o = uniform(wave_or32((uint32_t)orv));
+    w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
+  }
+
+  // a7: bit-plane transpose; element t of the lane goes to row t ^ 7 so that
+  // the first element of each byte lands in its most significant bit.
+  uint32_t lo[16], hi[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    lo[i] = (uint32_t)e[i ^ 7];
+    hi[i] = sizeof(U) == 8 ? (uint32_t)((uint64_t)e[i ^ 7] >> 32) : 0u;
+  }
+  xpose16(lo);
+  if constexpr (sizeof(U) == 8) xpose16(hi);
+
+  // a8-a9: per-row zero-byte counts, scheme flags, chunk size
+  uint64_t flags = 0;
+  uint32_t rows = 0;
+  for_planes_down<T::W - 1>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p < (int)w) {
+      const uint32_t fld = plane_field<T, p>(lo, hi);
+      const uint64_t E = ballot((fld & 0xFFu) != 0), O = ballot((fld & 0xFF00u) != 0);
+      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+      // lambda = 128 - nnz zero bytes; sparse iff lambda > 16 (ties dense)
+      const bool dense = nnz >= 112;
+      flags |= (uint64_t)dense << p;
+      rows += dense ? 128u : 16u + nnz;
+    }
+  });
+  const uint32_t nflag = (w + 7) >> 3;
+  const uint32_t hlen = 3 + T::ZB + nflag;
+  const uint32_t S = hlen + rows;
+
+  // a10: exclusive prefix of the chunk sizes (decoupled look-back)
+  const uint64_t off = lookback(status, tglob, tglob - c, S, epoch, lane);
+
+  // a11: assemble the payload in LDS at the destination's 16-byte phase and
+  // copy it out with aligned 16-byte stores (byte stores at the two edges).
+  uint8_t* payload = sd.out + kHdrBytes + 4 * nc;
+  uint8_t* dst = payload + off;
+  const uint32_t pad = (uint32_t)((uintptr_t)dst & 15u);
+  if (lane < (int)hlen) {
+    uint32_t byte;
+    if (lane == 0) byte = (uint32_t)A;
+    else if (lane == 1) byte = (uint32_t)B;
+    else if (lane < 2 + T::ZB) byte = (uint32_t)((uint64_t)z1 >> (8 * (lane - 2))) & 0xFFu;
+    else if (lane == 2 + T::ZB) byte = w;
+    else byte = (uint32_t)(flags >> (8 * (nflag - 1 - (lane - 3 - T::ZB)))) & 0xFFu;
+    buf[pad + lane] = (uint8_t)byte;
+  }
+  uint32_t cur = pad + hlen;
+  for_planes_down<T::W - 1>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p < (int)w) {
+      const uint32_t fld = plane_field<T, p>(lo, hi);
+      const uint32_t b0 = fld & 0xFFu, b1 = fld >> 8;
+      if ((flags >> p) & 1) {
+        buf[cur + 2 * lane] = (uint8_t)b0;
+        buf[cur + 2 * lane + 1] = (uint8_t)b1;
+        cur += 128;
+      } else {
+        const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
+        // bitmap byte q covers row bytes 8q..8q+7, i.e. lanes 4q..4q+3
+        uint32_t bits = (((b0 != 0) ? 2u : 0u) | ((b1 != 0) ? 1u : 0u)) << (6 - 2 * (lane & 3));
+        bits |= shfl_xor32(bits, 1);
+        bits |= shfl_xor32(bits, 2);
+        if ((lane & 3) == 0) buf[cur + (lane >> 2)] = (uint8_t)bits;
+        const uint32_t rank = mbcnt(E) + mbcnt(O);
+        if (b0) buf[cur + 16 + rank] = (uint8_t)b0;
+        if (b1) buf[cur + 16 + rank + (b0 ? 1 : 0)] = (uint8_t)b1;
+        cur += 16u + (uint32_t)(__popcll(E) + __popcll(O));
+      }
+    }
+  });
+  wave_lds_sync();
+  {
+    const uint32_t total = pad + S;
+    uint8_t* dal = dst - pad;
+    const uint32_t nblk = (total + 15) >> 4;
+    for (uint32_t i = lane; i < nblk; i += 64) {
+      const uint32_t b_lo = i << 4, b_hi = b_lo + 16;
+      if (b_lo >= pad && b_hi <= total) {
+        *reinterpret_cast<uint4*>(dal + b_lo) = *reinterpret_cast<const uint4*>(buf + b_lo);
+      } else {
+        const uint32_t from = b_lo > pad ? b_lo : pad, to = b_hi < total ? b_hi : total;
+        for (uint32_t b = from; b < to; ++b) dal[b] = buf[b];
+      }
+    }
+  }
+  if (lane == 0) reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = S;
+  if (c == nc - 1) write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Decompression of one chunk (Sec. 4, executed by one wave)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const DecompressSeries& sd, uint64_t c,
+                                 uint64_t nc, uint64_t tglob, uint64_t* status, uint32_t epoch, int lane,
+                                 Ctl* ctl) {
+  using U = typename T::U;
+  using F = typename T::F;
+  using S_ = typename T::S;
+  const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
+  const uint32_t S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
+  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB);
+  const uint64_t agg = bad ? 0 : S;
+  // d1: chunk offset = exclusive prefix of the size array (look-back)
+  const uint64_t off = lookback(status, tglob, tglob - c, agg, epoch, lane);
+  if (off + agg > sd.payload_bytes) bad = true;
+  if (c == nc - 1 && off + agg != sd.payload_bytes) bad = true;
+  if (bad) {
+    if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  // stage the payload bytes in LDS at their 16-byte phase
+  const uint8_t* src = payload + off;
+  const uint32_t pad = (uint32_t)((uintptr_t)src & 15u);
+  const uint32_t total = pad + S;
+  {
+    const uint8_t* sal = src - pad;
+    const uint32_t nblk = (total + 15) >> 4;
+    for (uint32_t i = lane; i < nblk; i += 64) {
+      const uint32_t b_lo = i << 4, b_hi = b_lo + 16;
+      if (b_lo >= pad && b_hi <= total) {
+        *reinterpret_cast<uint4*>(buf + b_lo) = *reinterpret_cast<const uint4*>(sal + b_lo);
+      } else {
+        const uint32_t from = b_lo > pad ? b_lo : pad, to = b_hi < total ? b_hi : total;
+        for (uint32_t b = from; b < to; ++b) buf[b] = sal[b];
+      }
+    }
+  }
+  wave_lds_sync();
+  // chunk header: alpha_max, beta_hat_max, z_1, w, scheme flags
+  const uint32_t hb = (lane < 24 && pad + lane < total) ? buf[pad + lane] : 0u;
+  const int A = __builtin_amdgcn_readlane((int)hb, 0);
+  const int B = __builtin_amdgcn_readlane((int)hb, 1);
+  U z1 = 0;
+#pragma unroll
+  for (int k = 0; k < T::ZB; ++k) z1 |= (U)(uint32_t)__builtin_amdgcn_readlane((int)hb, 2 + k) << (8 * k);
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)hb, 2 + T::ZB);
+  if (w > (uint32_t)T::W) bad = true;
+  const uint32_t nflag = (w + 7) >> 3;
+  if (3 + T::ZB + nflag > S) bad = true;
+  uint64_t flags = 0;
+  if (!bad) {
+    for (uint32_t f = 0; f < nflag; ++f)
+      flags = (flags << 8) | (uint32_t)__builtin_amdgcn_readlane((int)hb, 3 + T::ZB + (int)f);
+  }
+  // d2: rows -> bit-plane fields of this lane (row bytes 2L, 2L+1)
+  uint32_t lo[16], hi[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lo[i] = hi[i] = 0;
+  uint32_t cur = pad + 3 + T::ZB + nflag;
+  const int q = lane >> 2, u2 = 2 * (lane & 3);
+  for_planes_down<T::W - 1>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (!bad && p < (int)w) {
+      uint32_t fld = 0;
+      if ((flags >> p) & 1) {
+        if (cur + 128 > total) {
+          bad = true;
+        } else {
+          fld = (uint32_t)buf[cur + 2 * lane] | ((uint32_t)buf[cur + 2 * lane + 1] << 8);
+          cur += 128;
+        }
+      } else if (cur + 16 > total) {
+        bad = true;
+      } else {
+        // 16-byte bitmap at an arbitrary byte offset: five aligned dwords
+        const uint32_t a0 = cur & ~3u, sh = (cur & 3u) * 8;
+        const uint32_t* d = reinterpret_cast<const uint32_t*>(buf + a0);
+        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+        const uint32_t m0 = sh ? (d0 >> sh) | (d1 << (32 - sh)) : d0;
+        const uint32_t m1 = sh ? (d1 >> sh) | (d2 << (32 - sh)) : d1;
+        const uint32_t m2 = sh ? (d2 >> sh) | (d3 << (32 - sh)) : d2;
+        const uint32_t m3 = sh ? (d3 >> sh) | (d4 << (32 - sh)) : d3;
+        const uint32_t p0 = __popc(m0), p1 = __popc(m1), p2 = __popc(m2), p3 = __popc(m3);
+        const uint32_t nnz = p0 + p1 + p2 + p3;
+        if (cur + 16 + nnz > total) {
+          bad = true;
+        } else {
+          const int di = q >> 2, bi = q & 3;
+          const uint32_t md = di == 0 ? m0 : di == 1 ? m1 : di == 2 ? m2 : m3;
+          const uint32_t before = (di > 0 ? p0 : 0) + (di > 1 ? p1 : 0) + (di > 2 ? p2 : 0) +
+                                  (uint32_t)__popc(md & ((1u << (8 * bi)) - 1u));
+          const uint32_t byteq = (md >> (8 * bi)) & 0xFFu;
+          const uint32_t nz0 = (byteq >> (7 - u2)) & 1u, nz1 = (byteq >> (6 - u2)) & 1u;
+          const uint32_t rank = before + (uint32_t)__popc(byteq >> (8 - u2));
+          const uint32_t b0 = nz0 ? buf[cur + 16 + rank] : 0u;
+          const uint32_t b1 = nz1 ? buf[cur + 16 + rank + nz0] : 0u;
+          fld = b0 | (b1 << 8);
+          cur += 16 + nnz;
+        }
+      }
+      plane_put<p>(lo, hi, fld);
+    }
+  });
+  if (cur != total) bad = true;
+  if (bad) {
+    if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wave_lds_sync();
+    return;
+  }
+  // d3: inverse transpose
+  xpose16(lo);
+  if constexpr (sizeof(U) == 8) xpose16(hi);
+  // d4: un-zigzag and prefix sum from g_1 = z_1 (modulo 2^W)
+  U gv[16];
+  U run = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    U et;
+    if constexpr (sizeof(U) == 8) et = ((uint64_t)hi[t ^ 7] << 32) | lo[t ^ 7];
+    else et = lo[t ^ 7];
+    run += unzigzag<U>(et);
+    gv[t] = run;
+  }
+  const uint64_t incl = wave_incl_scan64((uint64_t)run, lane);
+  const U basev = (U)(z1 + (U)(incl - (uint64_t)run));
+  // d5: inverse Eq. 3, then coalesced store of the first nv values
+  const bool case1 = A <= T::AMAX && B <= T::BMAX;
+  const F P = T::pow10(sm, case1 ? A : 0);
+  wave_lds_sync();
+  U* vals = reinterpret_cast<U*>(buf);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const U gt = (U)(basev + gv[t]);
+    const U bits = case1 ? T::u((F)(S_)gt / P) : unzigzag<U>(gt);
+    const uint32_t i = 16u * lane + 1 + t;
+    vals[i + (i >> 4)] = bits;
+  }
+  const U v1 = case1 ? T::u((F)(S_)z1 / P) : unzigzag<U>(z1);
+  wave_lds_sync();
+  const uint64_t base = c * kChunk;
+  const uint64_t rem = sd.n - base;
+  const uint32_t nv = rem < (uint64_t)kChunk ? (uint32_t)rem : (uint32_t)kChunk;
+  U* out = reinterpret_cast<U*>(sd.out) + base;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t i = 1 + 64 * k + lane;
+    if (i < nv) __builtin_nontemporal_store(vals[i + (i >> 4)], out + i);
+  }
+  if (lane == 0) out[0] = v1;
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <class Series>
+__device__ __forceinline__ const Series& find_series(const Series& one, const Series* many, uint32_t ns,
+                                                     uint64_t t, Series& tmp) {
+  if (ns <= 1) return one;
+  uint32_t lo = 0, hi = ns - 1;  // last series with chunk0 <= t
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (many[mid].chunk0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  tmp = many[lo];
+  return tmp;
+}
+
+__device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, int lane) {
+  if (lane == 0) {
+    const uint32_t e = atomicAdd(&ctl->exited, 1u);
+    if (e + 1 == total_waves) {
+      __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compress(CompressArgs a) {
+  __shared__ BlockLds sm;
+  load_tables(sm);
+  __syncthreads();
+  const int lane = lane_id();
+  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&a.ctl->ticket, 1u);
+    t = uniform(t);
+    if (t >= a.total_chunks) {
+      if (t == 0 && a.nseries == 1) write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
+      break;
+    }
+    CompressSeries tmp;
+    const CompressSeries& sd = find_series(a.one, a.many, a.nseries, t, tmp);
+    const uint64_t c = t - sd.chunk0;
+    const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+    if (sd.dtype == 2) compress_chunk<TF64>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane);
+    else compress_chunk<TF32>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane);
+  }
+  exit_protocol(a.ctl, a.total_waves, lane);
+}
+
+__global__ __launch_bounds__(kBlock) void k_decompress(DecompressArgs a) {
+  __shared__ BlockLds sm;
+  load_tables(sm);
+  __syncthreads();
+  const int lane = lane_id();
+  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&a.ctl->ticket, 1u);
+    t = uniform(t);
+    if (t >= a.total_chunks) break;
+    DecompressSeries tmp;
+    const DecompressSeries& sd = find_series(a.one, a.many, a.nseries, t, tmp);
+    const uint64_t c = t - sd.chunk0;
+    const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+    if (sd.dtype == 2) decompress_chunk<TF64>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
+    else decompress_chunk<TF32>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
+  }
+  exit_protocol(a.ctl, a.total_waves, lane);
+}
+
+__global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_compress(const CompressArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_compress, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_decompress(const DecompressArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_decompress, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+static int max_grid_of(const void* fn, int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return per_cu * prop.multiProcessorCount;
+}
+int max_grid_compress(int device) { return max_grid_of(reinterpret_cast<const void*>(&k_compress), device); }
+int max_grid_decompress(int device) {
+  return max_grid_of(reinterpret_cast<const void*>(&k_decompress), device);
+}
+
+}  // namespace falcon_dev

@@ -22,6 +22,10 @@ from __future__ import annotations
 import numpy as np
 
 SEGMENT = 65536
+_POW10 = np.array([10.0 ** k for k in range(23)])   # exact for k <= 22
+# one period of the sinusoids, sin(2 pi t / P) for t = 0..P-1
+_SIN_1E4 = np.sin(2.0 * np.pi * np.arange(10000) / 1e4)
+_SIN_4096 = np.sin(2.0 * np.pi * np.arange(4096) / 4096.0)
 
 
 def walk_f64(n: int = 1 << 20, seed: int = 1) -> np.ndarray:
@@ -47,8 +51,14 @@ def _specials(rng: np.random.Generator, k: int) -> np.ndarray:
     return out.astype(np.uint64).view(np.float64)
 
 
+def _pool():
+    import concurrent.futures
+    import os
+    return concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)))
+
+
 def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
-               special_rate: float = 1e-5, block_segments: int = 64) -> np.ndarray:
+               special_rate: float = 1e-5, block_segments: int = 16) -> np.ndarray:
     """Sensor-like float64 series in 65,536-value segments.
 
     Each segment keeps d ~ U{1..6} decimal places; values are
@@ -56,95 +66,99 @@ def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
     outlier_rate of positions carries the unrounded value times
     (1 + U(-1e-3, 1e-3)), i.e. 16-17 significant digits; a fraction
     special_rate is replaced by a special value (NaN with payload, +-Inf,
-    -0.0, subnormal).
+    -0.0, subnormal).  Blocks of block_segments segments draw from their own
+    generator seeded with (seed, block), so the result does not depend on
+    the number of threads.
     """
-    rng = np.random.default_rng(seed)
     out = np.empty(n, np.float64)
-    walk0 = 0.0
     step = block_segments * SEGMENT
-    for lo in range(0, n, step):
-        hi = min(n, lo + step)
+    blocks = [(b, lo, min(n, lo + step)) for b, lo in enumerate(range(0, n, step))]
+
+    def walk(blk):
+        b, lo, hi = blk
+        rng = np.random.default_rng([seed, b])
+        inc = rng.standard_normal(hi - lo, dtype=np.float32) * np.float32(0.05)
+        np.cumsum(inc, dtype=np.float64, out=out[lo:hi])
+        return float(out[hi - 1])
+
+    def finish(blk, offset):
+        b, lo, hi = blk
         m = hi - lo
-        t = np.arange(lo, hi, dtype=np.float64)
-        walk = walk0 + np.cumsum(rng.normal(0.0, 0.05, m))
-        walk0 = float(walk[-1])
-        x = 100.0 * np.sin(2.0 * np.pi * t / 1e4) + walk
+        rng = np.random.default_rng([seed, b, 1])
+        x = 100.0 * _SIN_1E4[np.arange(lo, hi) % 10000] + (out[lo:hi] + offset)
         nseg = (m + SEGMENT - 1) // SEGMENT
-        d = np.repeat(rng.integers(1, 7, nseg), SEGMENT)[:m].astype(np.float64)
-        scale = 10.0 ** d
+        scale = np.repeat(_POW10[rng.integers(1, 7, nseg)], SEGMENT)[:m]
         v = np.rint(x * scale) / scale + 0.0
         outl = rng.random(m) < outlier_rate
         v[outl] = x[outl] * (1.0 + rng.uniform(-1e-3, 1e-3, int(outl.sum())))
         spec = rng.random(m) < special_rate
         v[spec] = _specials(rng, int(spec.sum()))
         out[lo:hi] = v
+
+    with _pool() as ex:
+        totals = list(ex.map(walk, blocks))
+        offsets = np.concatenate([[0.0], np.cumsum(totals)[:-1]]) if blocks else []
+        list(ex.map(finish, blocks, offsets))
     return out
 
 
-def _field_f32(rng: np.random.Generator, count: int, side: int = 512, lattice: int = 17,
-               start: int = 0) -> np.ndarray:
-    """count values (x fastest, from flat index start) of a side^3 field built
-    by tri-linear interpolation of a random lattice^3 grid plus a
-    U(-1e-3, 1e-3) perturbation at full binary32 precision."""
-    grid = rng.standard_normal((lattice, lattice, lattice))
-    out = np.empty(count, np.float32)
+def _field_f32(rng_seed, count: int, side: int = 512, lattice: int = 17, ex=None) -> np.ndarray:
+    """The first count values (x fastest) of a side^3 field built by
+    tri-linear interpolation of a random lattice^3 grid plus a
+    U(-1e-3, 1e-3) perturbation at full binary32 precision.  The
+    interpolation is done axis by axis (z, then y, then x), which is the
+    same tri-linear weight product evaluated in a fixed order."""
+    grid = np.random.default_rng(list(rng_seed)).standard_normal((lattice, lattice, lattice))
     coords = np.arange(side, dtype=np.float64) * (lattice - 1) / (side - 1)
     i0 = np.minimum(coords.astype(np.int64), lattice - 2)
     f = coords - i0
+    out = np.empty(count, np.float32)
     plane = side * side
-    pos = 0
-    flat = start
-    while pos < count:
-        z = flat // plane
-        take = min(count - pos, plane - flat % plane)
-        idx = np.arange(flat % plane, flat % plane + take)
-        y = idx // side
-        x = idx % side
-        iz, fz = i0[z], f[z]
-        iy, fy = i0[y], f[y]
-        ix, fx = i0[x], f[x]
-        acc = np.zeros(take)
-        for dz in (0, 1):
-            wz = fz if dz else 1.0 - fz
-            for dy in (0, 1):
-                wy = fy if dy else 1.0 - fy
-                for dx in (0, 1):
-                    wx = fx if dx else 1.0 - fx
-                    acc += wz * wy * wx * grid[iz + dz, iy + dy, ix + dx]
-        pert = rng.uniform(-1e-3, 1e-3, take)
-        out[pos:pos + take] = (acc + pert).astype(np.float32)
-        pos += take
-        flat += take
+
+    def one(z):
+        gz = (1.0 - f[z]) * grid[i0[z]] + f[z] * grid[i0[z] + 1]           # (y, x) lattice
+        rows = (1.0 - f)[:, None] * gz[i0] + f[:, None] * gz[i0 + 1]       # side x lattice
+        vals = (1.0 - f)[None, :] * rows[:, i0] + f[None, :] * rows[:, i0 + 1]  # side x side
+        take = min(plane, count - z * plane)
+        pert = np.random.default_rng(list(rng_seed) + [z]).uniform(-1e-3, 1e-3, take)
+        out[z * plane:z * plane + take] = (vals.reshape(-1)[:take] + pert).astype(np.float32)
+
+    list(ex.map(one, range((count + plane - 1) // plane)))
     return out
 
 
 def mixed_f32(n: int = 1 << 29, seed: int = 3, side: int = 512) -> np.ndarray:
     """float32 set: first half smooth sinusoid plus N(0, 0.01^2) noise at
     d ~ U{0..4} places per 65,536-value segment; second half an HPC-like
-    field with full-precision mantissas (two side^3 fields, x fastest)."""
-    rng = np.random.default_rng(seed)
+    field with full-precision mantissas (side^3 fields, x fastest, as many
+    as needed: two for the full-size set)."""
     half = n // 2
     out = np.empty(n, np.float32)
-    step = 64 * SEGMENT
-    for lo in range(0, half, step):
+    step = 16 * SEGMENT
+
+    def smooth(blk):
+        b, lo = blk
         hi = min(half, lo + step)
         m = hi - lo
-        t = np.arange(lo, hi, dtype=np.float64)
-        x = np.sin(2.0 * np.pi * t / 4096.0) + rng.normal(0.0, 0.01, m)
+        rng = np.random.default_rng([seed, b])
+        x = (_SIN_4096[np.arange(lo, hi) % 4096] +
+             rng.standard_normal(m, dtype=np.float32).astype(np.float64) * 0.01)
         nseg = (m + SEGMENT - 1) // SEGMENT
-        d = np.repeat(rng.integers(0, 5, nseg), SEGMENT)[:m]
-        mant = np.rint(x * 10.0 ** d).astype(np.float32)
-        out[lo:hi] = mant / (10.0 ** d).astype(np.float32) + np.float32(0.0)
-    rest = n - half
-    per_field = side ** 3
-    pos = 0
-    fid = 0
-    while pos < rest:
-        take = min(rest - pos, per_field)
-        frng = np.random.default_rng([seed, fid])
-        out[half + pos:half + pos + take] = _field_f32(frng, take, side=side)
-        pos += take
-        fid += 1
+        scale = np.repeat(_POW10[rng.integers(0, 5, nseg)], SEGMENT)[:m]
+        mant = np.rint(x * scale).astype(np.float32)
+        out[lo:hi] = mant / scale.astype(np.float32) + np.float32(0.0)
+
+    with _pool() as ex:
+        list(ex.map(smooth, enumerate(range(0, half, step))))
+        rest = n - half
+        per_field = side ** 3
+        pos = 0
+        fid = 0
+        while pos < rest:
+            take = min(rest - pos, per_field)
+            out[half + pos:half + pos + take] = _field_f32((seed, 100 + fid), take, side=side, ex=ex)
+            pos += take
+            fid += 1
     return out
 
 
