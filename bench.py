@@ -1,0 +1,197 @@
+"""Benchmark of the Falcon hot path on one MI355X.
+
+One step = one pass of the whole path over the workload already resident in
+HBM: compress (integer conversion, delta + zigzag, adaptive bit-plane
+encoding, look-back offsets, stream compaction) followed by decompress
+(offsets, bit-plane decoding, inverse transforms).  Workload: 268,435,456
+float64 sensor-like values (2 GiB, 65,536-value segments at 1-6 decimal
+places, 1% full-precision outliers, specials at 1e-5), seeded synthetic.
+
+Prints one JSON line.  `value` is the round-trip throughput: original bytes
+per step divided by the step time.  Compress and decompress throughputs
+(the paper's CT and DT, here device-resident) and the compression ratio are
+reported beside it.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "compress/decompress GB/s + ratio; batched vs per-series launch; p99 latency"
+WORKLOAD = ("sensor_f64: 268,435,456 float64 values (2 GiB) in 65,536-value segments, "
+            "1-6 decimal places per segment, sinusoid + random walk, 1% full-precision "
+            "outliers, NaN/+-Inf/-0.0/subnormal at 1e-5")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for rel in ("paper_2511_04140_amd/csrc/kernels.hip", "paper_2511_04140_amd/csrc/codec_device.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, per_launch_algo_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_digest") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x, budget_s=12.0):
+    """The oracle as it stands, single-threaded, on the leading chunks of the
+    same workload until about budget_s seconds of work have been done."""
+    from oracle import oracle
+    import numpy as np
+    step = 2048 * 1025
+    done = 0
+    tc = td = 0.0
+    t_start = time.perf_counter()
+    while done < x.size and time.perf_counter() - t_start < budget_s:
+        part = np.ascontiguousarray(x[done:done + step])
+        t0 = time.perf_counter()
+        s = oracle.compress(part)
+        t1 = time.perf_counter()
+        y = oracle.decompress(s)
+        t2 = time.perf_counter()
+        assert np.array_equal(y.view(np.uint8), part.view(np.uint8))
+        tc += t1 - t0
+        td += t2 - t1
+        done += part.size
+    nbytes = done * x.itemsize
+    return {
+        "value": round(nbytes / (tc + td) / 1e9, 6),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {done:,} values ({nbytes / 2**20:.0f} MiB) of the workload, "
+                  f"compress + decompress, single thread",
+        "compress_gbps": round(nbytes / tc / 1e9, 6),
+        "decompress_gbps": round(nbytes / td / 1e9, 6),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 28, help="values (default: the 2 GiB workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this codec's multi-GPU "
+              "sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    x = W.sensor_f64(args.n, seed=2)
+    xd = torch.from_numpy(x).to(dev)
+    nbytes = x.nbytes
+    codec = C.Codec(0)
+    cap = C.compress_bound(x.size, torch.float64)
+    sbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    ybuf = torch.empty_like(xd)
+
+    # warm-up (first pass also checks the round trip)
+    for i in range(args.warmup):
+        s = codec.compress(xd, out=sbuf)
+        y = codec.decompress(s, out=ybuf)
+        if i == 0:
+            assert torch.equal(y.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
+    torch.cuda.synchronize()
+
+    kc, kd = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = codec.compress(xd, out=sbuf)
+        kc.append(codec.last_kernel_ms())
+        y = codec.decompress(s, out=ybuf)
+        kd.append(codec.last_kernel_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert torch.equal(ybuf.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
+
+    clen = s.numel()
+    ratio = clen / nbytes
+    step_s = (t1 - t0) / args.steps
+    kc_ms, kd_ms = float(np.mean(kc)), float(np.mean(kd))
+    algo_c = nbytes + clen          # read the values, write the stream
+    algo_d = clen + nbytes          # read the stream, write the values
+    dominant = "k_compress" if kc_ms >= kd_ms else "k_decompress"
+    dom_ms = max(kc_ms, kd_ms)
+    achieved = (algo_c if dominant == "k_compress" else algo_d) / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, algo_c)
+
+    # fraction of chunks in each case of Eq. 3 (header byte alpha_max <= 22)
+    nc = (x.size + 1024) // 1025
+    sizes = s[32:32 + 4 * nc].view(torch.int32).to(torch.int64)
+    offs = torch.cumsum(sizes, 0) - sizes
+    a_bytes = s[32 + 4 * nc + offs]
+    b_bytes = s[32 + 4 * nc + offs + 1]
+    case1 = float(((a_bytes <= 22) & (b_bytes <= 15)).float().mean().item())
+
+    out = {
+        "metric": METRIC,
+        "value": round(nbytes / step_s / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": int(x.size), "bytes": int(nbytes),
+                   "chunk": 1025, "resident": "HBM"},
+        "compress_gbps": round(nbytes / (kc_ms * 1e-3) / 1e9, 3),
+        "decompress_gbps": round(nbytes / (kd_ms * 1e-3) / 1e9, 3),
+        "ratio": round(ratio, 6),
+        "case1_chunk_fraction": round(case1, 6),
+        "kernel_ms": {"k_compress": round(kc_ms, 4), "k_decompress": round(kd_ms, 4)},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+        },
+        "roofline_other": {
+            "kernel": "k_decompress" if dominant == "k_compress" else "k_compress",
+            "achieved": round((algo_d if dominant == "k_compress" else algo_c) /
+                              (min(kc_ms, kd_ms) * 1e-3) / 1e9, 2),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x)
+    codec.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

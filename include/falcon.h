@@ -99,6 +99,12 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
  * a version-1 Falcon header. */
 falcon_status falcon_stream_info(const void* h_hdr, size_t len, size_t* n, falcon_dtype* dt);
 
+/* Duration in milliseconds of the last compression or decompression kernel
+ * launched through ctx, measured with HIP events recorded on the launch
+ * stream immediately before and after the kernel.  Intended for roofline
+ * accounting; FALCON_ERR_INVALID_ARG if no kernel has run yet. */
+falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms);
+
 /* Static, human-readable name of a status code. */
 const char* falcon_status_str(falcon_status st);
 

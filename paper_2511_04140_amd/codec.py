@@ -48,6 +48,8 @@ def _load():
     L.falcon_decompress.restype = i
     L.falcon_stream_info.argtypes = [vp, sz, ctypes.POINTER(sz), ctypes.POINTER(i)]
     L.falcon_stream_info.restype = i
+    L.falcon_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.falcon_last_kernel_ms.restype = i
     L.falcon_status_str.argtypes = [i]
     L.falcon_status_str.restype = ctypes.c_char_p
     return L
@@ -102,6 +104,14 @@ class Codec:
             self.close()
         except Exception:
             pass
+
+    def last_kernel_ms(self) -> float:
+        """Duration of the last kernel this codec launched (HIP events)."""
+        ms = ctypes.c_float()
+        st = lib().falcon_last_kernel_ms(self._ctx, ctypes.byref(ms))
+        if st != 0:
+            raise FalconError(st, "falcon_last_kernel_ms")
+        return ms.value
 
     def compress(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Compresses a contiguous float32/float64 device tensor; returns the

@@ -35,6 +35,8 @@ struct falcon_ctx {
   uint8_t* stage = nullptr;     // pinned host staging (64 bytes)
   uint32_t epoch = 0;
   int grid_c = 0, grid_d = 0;   // co-resident workgroups of each kernel
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last kernel launch
+  bool timed = false;
 };
 
 namespace {
@@ -103,7 +105,8 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
   ctx->device = device;
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc(&ctx->ctl, 64) != hipSuccess || hipMemset(ctx->ctl, 0, 64) != hipSuccess ||
-      hipHostMalloc(&ctx->stage, 64, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&ctx->stage, 64, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
@@ -120,6 +123,8 @@ void falcon_destroy(falcon_ctx* ctx) {
   if (ctx->status) (void)hipFree(ctx->status);
   if (ctx->ctl) (void)hipFree(ctx->ctl);
   if (ctx->stage) (void)hipHostFree(ctx->stage);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -162,7 +167,11 @@ falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falco
   a.epoch = ctx->epoch;
   const int grid = grid_for(ctx->grid_c, nc);
   a.total_waves = (uint32_t)(grid * kWavesPerBlock);
+  ctx->timed = false;
+  if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   if ((st = dev_err(launch_compress(a, grid, s))) != FALCON_OK) return st;
+  if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
+  ctx->timed = true;
   if ((st = dev_err(hipMemcpyAsync(ctx->stage, static_cast<uint8_t*>(d_out) + 24, 8, hipMemcpyDeviceToHost, s))) !=
       FALCON_OK)
     return st;
@@ -208,12 +217,22 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
   a.epoch = ctx->epoch;
   const int grid = grid_for(ctx->grid_d, nc);
   a.total_waves = (uint32_t)(grid * kWavesPerBlock);
+  ctx->timed = false;
+  if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   if ((st = dev_err(launch_decompress(a, grid, s))) != FALCON_OK) return st;
+  if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
+  ctx->timed = true;
   if ((st = dev_err(hipMemcpyAsync(ctx->stage + 32, &ctx->ctl->error, 4, hipMemcpyDeviceToHost, s))) != FALCON_OK)
     return st;
   if ((st = dev_err(hipStreamSynchronize(s))) != FALCON_OK) return st;
   if (rd32(ctx->stage + 32) == ctx->epoch) return FALCON_ERR_CORRUPT_STREAM;
   return FALCON_OK;
+}
+
+falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms) {
+  if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
+  if (hipEventSynchronize(ctx->ev1) != hipSuccess) return FALCON_ERR_DEVICE;
+  return dev_err(hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
 }
 
 }  // extern "C"

@@ -1,0 +1,159 @@
+"""The GPU decides a chunk's case (Eq. 3) without running Alg. 2 value by
+value: it tests every value once at the chunk's largest admissible scale
+L* = min(AMAX, BMAX - 1 - FL10(v_max)), bisects alpha_max below it, and
+checks a failing value at its own limit (see decide_case in kernels.hip).
+This test restates that procedure with numpy, independently of the HIP
+code, and checks that on adversarial chunks it reaches the header (A, B)
+the oracle's literal Alg. 2 gives.  Chunks the procedure hands to the
+literal fallback are counted, not compared (they take the literal path on
+the GPU too)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+
+def _pow10_table(mant_bits, lo, hi):
+    out = {}
+    for k in range(lo, hi + 1):
+        q = Fraction(10) ** k
+        out[k] = float(q) if mant_bits == 52 else np.float32(float(q))
+    return out
+
+
+class Spec:
+    def __init__(self, dt):
+        self.dt = np.dtype(dt)
+        if self.dt == np.float64:
+            self.U, self.A, self.B, self.M, self.bias, self.mu = np.uint64, 22, 15, 52, 1023, 2.0 ** -52
+            self.P = _pow10_table(52, -22, 22)
+        else:
+            self.U, self.A, self.B, self.M, self.bias, self.mu = np.uint32, 10, 6, 23, 127, np.float32(2.0 ** -23)
+            self.P = {k: np.float32(v) for k, v in _pow10_table(23, -10, 10).items()}
+        self.F = self.dt.type
+
+    def bits(self, v):
+        return np.asarray(v, self.dt).view(self.U)
+
+    def mag(self, b):
+        return b & self.U((1 << (self.dt.itemsize * 8 - 1)) - 1)
+
+    def fl10(self, magbits):
+        e2 = ((magbits >> self.U(self.M)).astype(np.int64)) - self.bias
+        k0 = (e2 * 78913) >> 18
+        thr = np.array([self.bits(self.P[int(k)])[()] for k in (k0 + 1).ravel()], self.U).reshape(k0.shape)
+        return k0 + (magbits >= thr)
+
+    def eps(self, v, P):
+        x = v * self.F(P)
+        r = np.rint(x)
+        return np.abs(x - r) <= np.abs(x) * self.F(self.mu), r
+
+    def full(self, v, P):
+        ok, r = self.eps(v, P)
+        with np.errstate(all="ignore"):
+            back = (r / self.F(P)).astype(self.dt)
+        return ok & (self.bits(back) == self.bits(v))
+
+
+def fast_decide(spec, v):
+    """Returns (A, B) or None for 'literal fallback'."""
+    b = spec.bits(v)
+    m = spec.mag(b)
+    lo, hi = spec.bits(spec.P[-spec.A])[()], spec.bits(spec.P[spec.B])[()]
+    if np.any((b != 0) & ((m < lo) | (m >= hi))):
+        return spec.A + 1, spec.B + 1
+    vmax = m.max()
+    if vmax == 0:
+        return 0, 0
+    maxfl = int(spec.fl10(np.array([vmax], spec.U))[0])
+    lstar = min(spec.A, spec.B - 1 - maxfl)
+    fail = ~spec.full(v, spec.P[lstar])
+    if not fail.any():
+        a, h = 0, lstar
+        while a < h:
+            mid = (a + h) // 2
+            ok, _ = spec.eps(v, spec.P[mid])
+            if ok.all():
+                h = mid
+            else:
+                a = mid + 1
+        if h != lstar and not spec.full(v, spec.P[h]).all():
+            return None
+        return h, h + maxfl + 1
+    fl = spec.fl10(m[fail])
+    lim = np.minimum(spec.A, spec.B - 1 - fl)
+    exc = lim == lstar
+    for i, (val, li) in enumerate(zip(v[fail], lim)):
+        if not exc[i] and not spec.full(np.array([val]), spec.P[int(li)])[0]:
+            exc[i] = True
+    if exc.any():
+        return spec.A + 1, spec.B + 1
+    return None
+
+
+def _chunks(dt, rng, count):
+    """Adversarial chunks: mixed decimal places and magnitudes, values next
+    to powers of ten, sums of short decimals, 15/16/17-digit values, tiny
+    and huge magnitudes, specials."""
+    n = 1025
+    out = []
+    for i in range(count):
+        kind = i % 9
+        if dt == np.float64:
+            maxd, maxdig = 22, 17
+        else:
+            maxd, maxdig = 10, 8
+        if kind == 0:
+            d = rng.integers(0, maxd + 1)
+            mag = 10.0 ** rng.integers(-3, 8)
+            v = np.rint(rng.uniform(-mag, mag, n) * 10.0 ** d) / 10.0 ** d
+        elif kind == 1:   # per-value decimal places
+            d = rng.integers(0, maxd // 2 + 1, n)
+            v = np.rint(rng.uniform(-100, 100, n) * 10.0 ** d) / 10.0 ** d
+        elif kind == 2:   # near powers of ten
+            k = rng.integers(-12, 14, n).astype(np.float64)
+            v = 10.0 ** k * (1 + rng.integers(-4, 5, n) * 2.0 ** -50)
+        elif kind == 3:   # sums of short decimals
+            v = np.rint(rng.uniform(-1, 1, n) * 1e2) / 1e2 + np.rint(rng.uniform(-1, 1, n) * 1e3) / 1e3
+        elif kind == 4:   # digits around the precision guard
+            dig = rng.integers(maxdig - 3, maxdig + 1)
+            mm = rng.integers(10 ** (dig - 1), 10 ** dig, n).astype(np.float64)
+            v = mm / 10.0 ** rng.integers(0, min(dig, maxd), n)
+        elif kind == 5:   # one outlier in a clean chunk
+            v = np.rint(rng.uniform(-50, 50, n) * 1e3) / 1e3
+            v[rng.integers(0, n)] = rng.uniform(-50, 50)
+        elif kind == 6:   # tiny magnitudes at the alpha limit
+            d = maxd - rng.integers(0, 4)
+            v = rng.integers(1, 100, n) / 10.0 ** d
+        elif kind == 7:   # big integers and small decimals mixed (beta_hat > BMAX)
+            v = np.where(rng.random(n) < 0.5, rng.integers(1, 10 ** (maxdig - 4), n).astype(np.float64),
+                         rng.integers(1, 100, n) / 10.0 ** 4)
+        else:             # random binary patterns
+            nb = 64 if dt == np.float64 else 32
+            v = rng.integers(0, 1 << nb, n, dtype=np.uint64, endpoint=False)
+            v = v.view(np.float64) if dt == np.float64 else v.astype(np.uint32).view(np.float32)
+        v = np.asarray(v, dt)
+        if dt == np.float32 and kind not in (8,):
+            v = np.asarray(v.astype(np.float64), np.float32)
+        out.append(np.where(v == 0, dt(0), v).astype(dt) + dt(0))
+    return out
+
+
+@pytest.mark.parametrize("dt,count", [(np.float64, 1800), (np.float32, 1800)])
+def test_fast_decision_matches_literal_alg2(orc, dt, count):
+    spec = Spec(dt)
+    rng = np.random.default_rng(20251105 + (dt == np.float32))
+    literal = 0
+    mismatches = []
+    for ch in _chunks(dt, rng, count):
+        with np.errstate(all="ignore"):
+            got = fast_decide(spec, ch)
+        A, B, w, _ = orc.chunk_info(ch)
+        if got is None:
+            literal += 1
+            continue
+        if got != (A, B):
+            mismatches.append((ch[:4], got, (A, B)))
+    assert not mismatches, mismatches[:5]
+    assert literal < count // 5
