@@ -29,12 +29,15 @@ uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
 struct falcon_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  uint64_t* status = nullptr;   // look-back status words
+  uint64_t* status = nullptr;   // look-back status words, one per chunk
   size_t status_cap = 0;
+  uint64_t* gstatus = nullptr;  // one per 64-chunk group
+  size_t gstatus_cap = 0;
   Ctl* ctl = nullptr;           // device control block
   uint8_t* stage = nullptr;     // pinned host staging (64 bytes)
   uint32_t epoch = 0;
-  int grid_c = 0, grid_d = 0;   // co-resident workgroups of each kernel
+  int grid_c[3] = {0, 0, 0};   // co-resident workgroups per kernel, by dtype
+  int grid_d[3] = {0, 0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last kernel launch
   bool timed = false;
 };
@@ -43,27 +46,38 @@ namespace {
 
 falcon_status dev_err(hipError_t e) { return e == hipSuccess ? FALCON_OK : FALCON_ERR_DEVICE; }
 
-// Makes the status array hold at least nchunks words and advances the epoch.
-falcon_status prepare_launch(falcon_ctx* ctx, uint64_t nchunks, hipStream_t s) {
-  if (nchunks > ctx->status_cap) {
-    size_t cap = ctx->status_cap ? ctx->status_cap : 1024;
-    while (cap < nchunks) cap *= 2;
-    // the stream may still use the old array: wait before freeing it
-    if (hipStreamSynchronize(s) != hipSuccess) return FALCON_ERR_DEVICE;
-    if (ctx->status) (void)hipFree(ctx->status);
-    ctx->status = nullptr;
-    ctx->status_cap = 0;
-    if (hipMalloc(&ctx->status, cap * sizeof(uint64_t)) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
-    ctx->status_cap = cap;
-    if (launch_fill_u64(ctx->status, cap, 0, s) != hipSuccess) return FALCON_ERR_DEVICE;
-  }
+// Grows a zeroed status array to at least n words.
+falcon_status grow_zeroed(uint64_t** arr, size_t* cap, uint64_t n, hipStream_t s) {
+  if (n <= *cap) return FALCON_OK;
+  size_t c = *cap ? *cap : 1024;
+  while (c < n) c *= 2;
+  // the stream may still use the old array: wait before freeing it
+  if (hipStreamSynchronize(s) != hipSuccess) return FALCON_ERR_DEVICE;
+  if (*arr) (void)hipFree(*arr);
+  *arr = nullptr;
+  *cap = 0;
+  if (hipMalloc(arr, c * sizeof(uint64_t)) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
+  *cap = c;
+  return launch_fill_u64(*arr, c, 0, s) == hipSuccess ? FALCON_OK : FALCON_ERR_DEVICE;
+}
+
+// Makes the status arrays hold nchunks chunk words and ngroups group words,
+// and advances the launch epoch.
+falcon_status prepare_launch(falcon_ctx* ctx, uint64_t nchunks, uint64_t ngroups, hipStream_t s) {
+  falcon_status st = grow_zeroed(&ctx->status, &ctx->status_cap, nchunks, s);
+  if (st == FALCON_OK) st = grow_zeroed(&ctx->gstatus, &ctx->gstatus_cap, ngroups, s);
+  if (st != FALCON_OK) return st;
   ctx->epoch += 1;
   if ((ctx->epoch & 0xFFFF) == 0) {  // epoch tag wrapped: clear old words
     ctx->epoch += 1;
-    if (launch_fill_u64(ctx->status, ctx->status_cap, 0, s) != hipSuccess) return FALCON_ERR_DEVICE;
+    if (launch_fill_u64(ctx->status, ctx->status_cap, 0, s) != hipSuccess ||
+        launch_fill_u64(ctx->gstatus, ctx->gstatus_cap, 0, s) != hipSuccess)
+      return FALCON_ERR_DEVICE;
   }
   return FALCON_OK;
 }
+
+uint64_t groups_of(uint64_t nchunks) { return (nchunks + 63) / 64; }
 
 int grid_for(int max_grid, uint64_t nchunks) {
   uint64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -110,8 +124,10 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
-  ctx->grid_c = max_grid_compress(device);
-  ctx->grid_d = max_grid_decompress(device);
+  for (int dt = 1; dt <= 2; ++dt) {
+    ctx->grid_c[dt] = max_grid_compress(device, dt);
+    ctx->grid_d[dt] = max_grid_decompress(device, dt);
+  }
   *out = ctx;
   return FALCON_OK;
 }
@@ -121,6 +137,7 @@ void falcon_destroy(falcon_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->status) (void)hipFree(ctx->status);
+  if (ctx->gstatus) (void)hipFree(ctx->gstatus);
   if (ctx->ctl) (void)hipFree(ctx->ctl);
   if (ctx->stage) (void)hipHostFree(ctx->stage);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -151,25 +168,27 @@ falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falco
   if (nc >= 0xFFFFFFF0ull) return FALCON_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
-  falcon_status st = prepare_launch(ctx, nc ? nc : 1, s);
+  falcon_status st = prepare_launch(ctx, nc ? nc : 1, groups_of(nc) + 1, s);
   if (st != FALCON_OK) return st;
   CompressArgs a{};
   a.one.in = d_in;
   a.one.out = static_cast<uint8_t*>(d_out);
   a.one.n = n;
   a.one.chunk0 = 0;
+  a.one.group0 = 0;
   a.one.dtype = (uint32_t)dt;
   a.many = nullptr;
   a.nseries = 1;
   a.total_chunks = nc;
   a.status = ctx->status;
+  a.gstatus = ctx->gstatus;
   a.ctl = ctx->ctl;
   a.epoch = ctx->epoch;
-  const int grid = grid_for(ctx->grid_c, nc);
+  const int grid = grid_for(ctx->grid_c[dt], nc);
   a.total_waves = (uint32_t)(grid * kWavesPerBlock);
   ctx->timed = false;
   if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
-  if ((st = dev_err(launch_compress(a, grid, s))) != FALCON_OK) return st;
+  if ((st = dev_err(launch_compress(a, (int)dt, grid, s))) != FALCON_OK) return st;
   if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
   ctx->timed = true;
   if ((st = dev_err(hipMemcpyAsync(ctx->stage, static_cast<uint8_t*>(d_out) + 24, 8, hipMemcpyDeviceToHost, s))) !=
@@ -201,25 +220,27 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
   if (out_cap_bytes / es < n) return FALCON_ERR_BUFFER_TOO_SMALL;
   if (n == 0) return payload == 0 ? FALCON_OK : FALCON_ERR_CORRUPT_STREAM;
   if (!d_out || ((uintptr_t)d_out % es)) return FALCON_ERR_INVALID_ARG;
-  if ((st = prepare_launch(ctx, nc, s)) != FALCON_OK) return st;
+  if ((st = prepare_launch(ctx, nc, groups_of(nc) + 1, s)) != FALCON_OK) return st;
   DecompressArgs a{};
   a.one.in = static_cast<const uint8_t*>(d_in);
   a.one.out = static_cast<uint8_t*>(d_out);
   a.one.n = n;
   a.one.chunk0 = 0;
+  a.one.group0 = 0;
   a.one.payload_bytes = payload;
   a.one.dtype = (uint32_t)dt;
   a.many = nullptr;
   a.nseries = 1;
   a.total_chunks = nc;
   a.status = ctx->status;
+  a.gstatus = ctx->gstatus;
   a.ctl = ctx->ctl;
   a.epoch = ctx->epoch;
-  const int grid = grid_for(ctx->grid_d, nc);
+  const int grid = grid_for(ctx->grid_d[dt], nc);
   a.total_waves = (uint32_t)(grid * kWavesPerBlock);
   ctx->timed = false;
   if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
-  if ((st = dev_err(launch_decompress(a, grid, s))) != FALCON_OK) return st;
+  if ((st = dev_err(launch_decompress(a, (int)dt, grid, s))) != FALCON_OK) return st;
   if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
   ctx->timed = true;
   if ((st = dev_err(hipMemcpyAsync(ctx->stage + 32, &ctx->ctl->error, 4, hipMemcpyDeviceToHost, s))) != FALCON_OK)

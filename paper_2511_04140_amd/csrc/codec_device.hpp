@@ -211,11 +211,12 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 }
 
 // Orders this wave's LDS accesses: writes before the barrier are visible to
-// reads of other lanes after it.
+// reads of other lanes after it.  The fence is restricted to LDS, so it does
+// not wait for outstanding global loads or stores.
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
 // ---------------------------------------------------------------------------
@@ -241,14 +242,26 @@ __device__ __forceinline__ void xpose16(uint32_t (&a)[16]) {
 }
 
 // ---------------------------------------------------------------------------
-// Decoupled look-back (Sec. 3.4: the compressed chunk sizes are synchronised
-// into offsets; the paper uses a decoupled look-back).  One 64-bit status
-// word per chunk: bits 63..48 launch epoch, 47..46 flag (1 = aggregate, the
-// chunk's own size; 2 = inclusive prefix), 45..0 value.  The epoch lets
-// successive launches reuse the array without clearing it.  The whole wave
-// inspects 64 predecessors at a time.  Returns the exclusive prefix.
+// Two-level decoupled look-back (Sec. 3.4: the compressed chunk sizes are
+// synchronised into offsets with a decoupled look-back).
+//
+// Status words, one per chunk and one per group of 64 consecutive chunks of
+// a series: bits 63..48 launch epoch, 47..46 flag (1 = aggregate: the
+// chunk's or group's own byte count; 2 = inclusive prefix), 45..0 value.
+// The epoch lets successive launches reuse the arrays without clearing them.
+//
+// A chunk publishes its aggregate, then reads the status of the chunks
+// before it in its group (one window of at most 63 lanes).  If one of them
+// already holds an inclusive prefix the answer follows directly.  Otherwise
+// the chunk needs the exclusive prefix of its group, which it finds by a
+// look-back over the group words (64 groups per window): the last chunk of
+// each group publishes the group aggregate as soon as it has summed its
+// window, and the group's inclusive prefix once it knows its own offset.
+// The depth of the walk is thus the number of groups in flight, not the
+// number of chunks in flight.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kValMask = (1ull << 46) - 1;
+constexpr uint32_t kFlagAgg = 1, kFlagPrefix = 2;
 
 __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -256,39 +269,87 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, uint64_t v) {
+  return ((uint64_t)(epoch & 0xFFFF) << 48) | ((uint64_t)flag << 46) | (v & kValMask);
+}
 
-__device__ __forceinline__ uint64_t lookback(uint64_t* status, uint64_t t, uint64_t first,
-                                             uint64_t agg, uint32_t epoch, int lane) {
-  const uint64_t tag = (uint64_t)(epoch & 0xFFFF) << 48;
-  if (t == first) {
-    if (lane == 0) status_store(status + t, tag | (2ull << 46) | agg);
-    return 0;
-  }
-  if (lane == 0) status_store(status + t, tag | (1ull << 46) | agg);
-  uint64_t excl = 0;
-  int64_t j = (int64_t)t - 1;
-  while (true) {
-    const int64_t idx = j - lane;
-    const bool valid = idx >= (int64_t)first;
-    const uint64_t s = valid ? status_load(status + idx) : 0;
-    const bool mine = (s >> 48) == (uint64_t)(epoch & 0xFFFF);
-    const uint32_t flag = (uint32_t)(s >> 46) & 3u;
-    const bool ready = !valid || (mine && flag != 0);
-    const bool isp = !valid || (mine && flag == 2);
-    const uint64_t pm = ballot(isp), nm = ballot(!ready);
-    const int firstp = pm ? (int)__builtin_ctzll(pm) : 64;
-    const uint64_t win = firstp >= 63 ? ~0ull : ((2ull << firstp) - 1);
-    if (nm & win) {
+// Window evaluation: lanes hold status words of consecutive predecessors,
+// nearest first (lane 0).  Returns false if a word needed for the answer is
+// not ready yet.  Otherwise sum = value of the nearest prefix word plus the
+// aggregates before it (or of all lanes if none is a prefix), found = whether
+// a prefix word was met.
+__device__ __forceinline__ bool window_sum(uint64_t s, bool valid, uint32_t epoch, uint64_t& sum, bool& found) {
+  const bool mine = (s >> 48) == (uint64_t)(epoch & 0xFFFF);
+  const uint32_t flag = (uint32_t)(s >> 46) & 3u;
+  const bool ready = !valid || (mine && flag != 0);
+  const bool isp = valid && mine && flag == kFlagPrefix;
+  const uint64_t pm = ballot(isp), nm = ballot(!ready);
+  const int firstp = pm ? (int)__builtin_ctzll(pm) : 64;
+  const uint64_t win = firstp >= 63 ? ~0ull : ((2ull << firstp) - 1);
+  if (nm & win) return false;
+  const int lane = lane_id();
+  sum = uniform64(wave_sum64((valid && lane <= firstp) ? (s & kValMask) : 0));
+  found = firstp < 64;
+  return true;
+}
+
+struct LookbackState {
+  uint64_t first_sample;  // status of chunk t-1-lane, loaded early
+};
+
+// Publishes the chunk aggregate and issues the load of the in-group window.
+// c is the chunk's index in its series, t its status index.
+__device__ __forceinline__ uint64_t lookback_begin(uint64_t* status, uint64_t t, uint64_t c, uint64_t agg,
+                                                   uint32_t epoch, int lane) {
+  const uint32_t j = (uint32_t)(c & 63);
+  if (lane == 0) status_store(status + t, status_word(epoch, c == 0 ? kFlagPrefix : kFlagAgg, agg));
+  return (lane < (int)j) ? status_load(status + t - 1 - lane) : 0;
+}
+
+// Completes the look-back; returns the chunk's exclusive prefix.  gstatus is
+// the group status array, gbase the index of the series' first group.
+__device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gstatus, uint64_t t, uint64_t c,
+                                                 uint64_t gbase, uint64_t agg, uint32_t epoch, int lane,
+                                                 uint64_t sample) {
+  if (c == 0) return 0;  // the prefix word was published by lookback_begin
+  const uint32_t j = (uint32_t)(c & 63);
+  const uint64_t g = c >> 6;
+  uint64_t intra = 0;
+  bool found = false;
+  if (j > 0) {
+    const bool valid = lane < (int)j;
+    while (!window_sum(sample, valid, epoch, intra, found)) {
       __builtin_amdgcn_s_sleep(1);
-      continue;
+      sample = valid ? status_load(status + t - 1 - lane) : 0;
     }
-    const uint64_t contrib = (valid && lane <= firstp) ? (s & kValMask) : 0;
-    excl += wave_sum64(contrib);
-    if (firstp < 64) break;
-    j -= 64;
   }
-  excl = uniform64(excl);
-  if (lane == 0) status_store(status + t, tag | (2ull << 46) | ((excl + agg) & kValMask));
+  uint64_t excl;
+  if (found) {
+    excl = intra;
+  } else {
+    if (j == 63 && lane == 0) status_store(gstatus + gbase + g, status_word(epoch, kFlagAgg, intra + agg));
+    uint64_t gx = 0;
+    int64_t k = (int64_t)g - 1;  // nearest group first
+    while (k >= 0) {
+      const int64_t idx = k - lane;
+      const bool valid = idx >= 0;
+      uint64_t s = valid ? status_load(gstatus + gbase + idx) : 0;
+      uint64_t part;
+      bool gfound;
+      while (!window_sum(s, valid, epoch, part, gfound)) {
+        __builtin_amdgcn_s_sleep(1);
+        s = valid ? status_load(gstatus + gbase + idx) : 0;
+      }
+      gx += part;
+      if (gfound) break;
+      k -= 64;
+    }
+    excl = gx + intra;
+  }
+  if (lane == 0) {
+    status_store(status + t, status_word(epoch, kFlagPrefix, excl + agg));
+    if (j == 63) status_store(gstatus + gbase + g, status_word(epoch, kFlagPrefix, excl + agg));
+  }
   return excl;
 }
 

@@ -25,7 +25,8 @@ struct CompressSeries {
   uint8_t* out;
   uint64_t n;
   uint64_t chunk0;
-  uint32_t dtype;  // 1 = f32, 2 = f64
+  uint64_t group0;   // index of the series' first 64-chunk group status word
+  uint32_t dtype;    // 1 = f32, 2 = f64
   uint32_t pad;
 };
 
@@ -34,6 +35,7 @@ struct DecompressSeries {
   uint8_t* out;
   uint64_t n;
   uint64_t chunk0;
+  uint64_t group0;
   uint64_t payload_bytes;
   uint32_t dtype;
   uint32_t pad;
@@ -45,7 +47,8 @@ struct CompressArgs {
   uint32_t nseries;
   uint32_t total_waves;
   uint64_t total_chunks;
-  uint64_t* status;
+  uint64_t* status;    // one word per chunk of the launch
+  uint64_t* gstatus;   // one word per 64-chunk group of each series
   Ctl* ctl;
   uint32_t epoch;
   uint32_t pad;
@@ -57,7 +60,8 @@ struct DecompressArgs {
   uint32_t nseries;
   uint32_t total_waves;
   uint64_t total_chunks;
-  uint64_t* status;
+  uint64_t* status;    // one word per chunk of the launch
+  uint64_t* gstatus;   // one word per 64-chunk group of each series
   Ctl* ctl;
   uint32_t epoch;
   uint32_t pad;
@@ -66,11 +70,11 @@ struct DecompressArgs {
 constexpr int kThreadsPerBlock = 256;
 constexpr int kWavesPerBlock = 4;
 
-hipError_t launch_compress(const CompressArgs& a, int grid, hipStream_t s);
-hipError_t launch_decompress(const DecompressArgs& a, int grid, hipStream_t s);
+hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s);
+hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
 // Largest number of co-resident workgroups of each kernel on the device.
-int max_grid_compress(int device);
-int max_grid_decompress(int device);
+int max_grid_compress(int device, int dtype);
+int max_grid_decompress(int device, int dtype);
 
 }  // namespace falcon_dev

@@ -48,46 +48,47 @@ __device__ __forceinline__ bool full_test(typename T::U b, typename T::F P) {
   return ok && T::u(r / P) == b;
 }
 
-// Literal Alg. 2 over the 17 values of this lane (lock-step over alpha).
-// Used only when the fast decision below cannot settle the chunk.  Returns
-// true if some value is an exception; otherwise amax gets the lane's
-// largest decimal place.
+// bit k of m |= c.  The shift amount is made opaque so that the compiler
+// builds the mask with a shift instead of keeping 1 << k constants in
+// registers.
+__device__ __forceinline__ void set_bit(uint32_t& m, bool c, int k) {
+  int kk = k;
+  asm volatile("" : "+s"(kk));
+  m |= (c ? 1u : 0u) << kk;
+}
+
+// Literal Alg. 2 over the 17 values of this lane, one slot at a time with
+// the lanes in lock-step over alpha.  Used only when the fast decision below
+// cannot settle the chunk.  Returns true if some value is an exception;
+// otherwise amax gets the lane's largest decimal place.
 template <class T>
-__device__ bool alg2_literal(const BlockLds& sm, const typename T::U (&vb)[17], int& amax) {
-  uint32_t pend = 0;
-  int lim[17];
+__device__ __forceinline__ bool alg2_literal(const BlockLds& sm, const typename T::U (&vb)[17], int& amax) {
   bool exc = false;
   amax = 0;
-#pragma unroll
   for (int k = 0; k < 17; ++k) {
-    lim[k] = 0;
-    if (vb[k] != 0) {
-      pend |= 1u << k;
-      const int f = fl10<T>(sm, T::mag(vb[k]));
-      lim[k] = min(T::AMAX, T::BMAX - 1 - f);  // beta = alpha + f + 1 <= BMAX
-    }
-  }
-  for (int a = 0; a <= T::AMAX; ++a) {
-    if (ballot(pend != 0) == 0) break;
-    const typename T::F P = T::pow10(sm, a);
-#pragma unroll
-    for (int k = 0; k < 17; ++k) {
-      if (pend & (1u << k)) {
-        if (a > lim[k]) {
+    const typename T::U v = vb[k];
+    bool done = v == 0;  // +0.0: alpha = 0
+    // loop condition of Alg. 2: beta = alpha + FL10 + 1 <= BMAX
+    const int lim = done ? 0 : min(T::AMAX, T::BMAX - 1 - fl10<T>(sm, T::mag(v)));
+    for (int a = 0; a <= T::AMAX; ++a) {
+      if (ballot(!done) == 0) break;
+      if (!done) {
+        if (a > lim) {
           exc = true;
-          pend &= ~(1u << k);
+          done = true;
         } else {
+          const typename T::F P = T::pow10(sm, a);
           typename T::F r;
-          if (eps_test<T>(vb[k], P, r)) {
-            pend &= ~(1u << k);
-            if (T::u(r / P) != vb[k]) exc = true;
+          if (eps_test<T>(v, P, r)) {
+            done = true;
+            if (T::u(r / P) != v) exc = true;
             else amax = max(amax, a);
           }
         }
       }
     }
+    if (!done) exc = true;
   }
-  if (pend) exc = true;
   return exc;
 }
 
@@ -113,7 +114,7 @@ __device__ bool alg2_literal(const BlockLds& sm, const typename T::U (&vb)[17], 
 //  4. Anything else (no exception found, alpha_max > L*, i.e. Case 2 with a
 //     real header) runs the literal Alg. 2.
 template <class T>
-__device__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], int& A, int& B,
+__device__ __forceinline__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], int& A, int& B,
                             bool& case1) {
   using U = typename T::U;
   using F = typename T::F;
@@ -146,8 +147,10 @@ __device__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], i
   {
     const F P = T::pow10(sm, lstar);
 #pragma unroll
-    for (int k = 0; k < 17; ++k)
-      if (!full_test<T>(vb[k], P)) fail |= 1u << k;
+    for (int k = 0; k < 17; ++k) {
+      F r;
+      set_bit(fail, !eps_test<T>(vb[k], P, r), k);
+    }
   }
   bool literal = false;
   if (ballot(fail != 0) == 0) {
@@ -164,7 +167,7 @@ __device__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], i
       if (ballot(bad)) lo = mid + 1;
       else hi = mid;
     }
-    if (hi != lstar) {
+    {
       const F P = T::pow10(sm, hi);
       bool bad = false;
 #pragma unroll
@@ -181,7 +184,7 @@ __device__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], i
     bool e = false;
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
-      if (fail & (1u << k)) {
+      if ((fail >> k) & 1u) {
         const int f = fl10<T>(sm, T::mag(vb[k]));
         const int lim = min(T::AMAX, T::BMAX - 1 - f);
         if (lim == lstar || !full_test<T>(vb[k], T::pow10(sm, lim))) e = true;
@@ -254,10 +257,16 @@ __device__ __forceinline__ void write_stream_header(uint8_t* out, uint32_t dtype
 // Compression of one chunk (Alg. 3 for one chunk, executed by one wave)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressSeries& sd, uint64_t c,
-                               uint64_t nc, uint64_t tglob, uint64_t* status, uint32_t epoch, int lane) {
+__device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressSeries& sd,
+                                               uint64_t c, uint64_t nc, uint64_t t, uint64_t* status,
+                                               uint64_t* gstatus, uint32_t epoch, int lane_in) {
   using U = typename T::U;
   using F = typename T::F;
+  // An opaque copy of the lane index keeps the compiler from hoisting the
+  // per-lane address arithmetic out of the ticket loop, where it would stay
+  // live (and spill) across every chunk.
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
   const U* in = reinterpret_cast<const U*>(sd.in);
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
@@ -310,9 +319,9 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
     const uint32_t b0 = 17u * lane;
     U prev = g[b0];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const U cur = g[b0 + 1 + t + (t == 15 ? 1 : 0)];
-      e[t] = zigzag<U>((U)(cur - prev));
+    for (int q = 0; q < 16; ++q) {
+      const U cur = g[b0 + 1 + q + (q == 15 ? 1 : 0)];
+      e[q] = zigzag<U>((U)(cur - prev));
       prev = cur;
     }
     z1 = g[0];
@@ -322,7 +331,7 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
   // a6: bit width w = W - min lead over z_2..z_n (lead of 0 is W)
   U orv = 0;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) orv |= e[t];
+  for (int q = 0; q < 16; ++q) orv |= e[q];
   uint32_t w;
   if constexpr (sizeof(U) == 8) {
     const uint64_t o = uniform64(wave_or64((uint64_t)orv));
@@ -332,7 +341,7 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
     w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
   }
 
-  // a7: bit-plane transpose; element t of the lane goes to row t ^ 7 so that
+  // a7: bit-plane transpose; element q of the lane goes to row q ^ 7 so that
   // the first element of each byte lands in its most significant bit.
   uint32_t lo[16], hi[16];
 #pragma unroll
@@ -343,54 +352,26 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
   xpose16(lo);
   if constexpr (sizeof(U) == 8) xpose16(hi);
 
-  // a8-a9: per-row zero-byte counts, scheme flags, chunk size
-  uint64_t flags = 0;
-  uint32_t rows = 0;
-  for_planes_down<T::W - 1>([&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    if (p < (int)w) {
-      const uint32_t fld = plane_field<T, p>(lo, hi);
-      const uint64_t E = ballot((fld & 0xFFu) != 0), O = ballot((fld & 0xFF00u) != 0);
-      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
-      // lambda = 128 - nnz zero bytes; sparse iff lambda > 16 (ties dense)
-      const bool dense = nnz >= 112;
-      flags |= (uint64_t)dense << p;
-      rows += dense ? 128u : 16u + nnz;
-    }
-  });
+  // a8-a9 and the first half of a11, in one pass over the planes: count the
+  // row's zero bytes, choose its scheme (sparse iff more than 16 of its 128
+  // bytes are zero; ties dense), and write it to LDS after the chunk header.
   const uint32_t nflag = (w + 7) >> 3;
   const uint32_t hlen = 3 + T::ZB + nflag;
-  const uint32_t S = hlen + rows;
-
-  // a10: exclusive prefix of the chunk sizes (decoupled look-back)
-  const uint64_t off = lookback(status, tglob, tglob - c, S, epoch, lane);
-
-  // a11: assemble the payload in LDS at the destination's 16-byte phase and
-  // copy it out with aligned 16-byte stores (byte stores at the two edges).
-  uint8_t* payload = sd.out + kHdrBytes + 4 * nc;
-  uint8_t* dst = payload + off;
-  const uint32_t pad = (uint32_t)((uintptr_t)dst & 15u);
-  if (lane < (int)hlen) {
-    uint32_t byte;
-    if (lane == 0) byte = (uint32_t)A;
-    else if (lane == 1) byte = (uint32_t)B;
-    else if (lane < 2 + T::ZB) byte = (uint32_t)((uint64_t)z1 >> (8 * (lane - 2))) & 0xFFu;
-    else if (lane == 2 + T::ZB) byte = w;
-    else byte = (uint32_t)(flags >> (8 * (nflag - 1 - (lane - 3 - T::ZB)))) & 0xFFu;
-    buf[pad + lane] = (uint8_t)byte;
-  }
-  uint32_t cur = pad + hlen;
+  uint64_t flags = 0;
+  uint32_t cur = hlen;
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
     if (p < (int)w) {
       const uint32_t fld = plane_field<T, p>(lo, hi);
       const uint32_t b0 = fld & 0xFFu, b1 = fld >> 8;
-      if ((flags >> p) & 1) {
+      const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
+      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+      if (nnz >= 112) {
+        flags |= 1ull << p;
         buf[cur + 2 * lane] = (uint8_t)b0;
         buf[cur + 2 * lane + 1] = (uint8_t)b1;
         cur += 128;
       } else {
-        const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
         // bitmap byte q covers row bytes 8q..8q+7, i.e. lanes 4q..4q+3
         uint32_t bits = (((b0 != 0) ? 2u : 0u) | ((b1 != 0) ? 1u : 0u)) << (6 - 2 * (lane & 3));
         bits |= shfl_xor32(bits, 1);
@@ -399,23 +380,59 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
         const uint32_t rank = mbcnt(E) + mbcnt(O);
         if (b0) buf[cur + 16 + rank] = (uint8_t)b0;
         if (b1) buf[cur + 16 + rank + (b0 ? 1 : 0)] = (uint8_t)b1;
-        cur += 16u + (uint32_t)(__popcll(E) + __popcll(O));
+        cur += 16u + nnz;
       }
     }
   });
+  const uint32_t S = cur;
+  if (lane < (int)hlen) {
+    uint32_t byte;
+    if (lane == 0) byte = (uint32_t)A;
+    else if (lane == 1) byte = (uint32_t)B;
+    else if (lane < 2 + T::ZB) byte = (uint32_t)((uint64_t)z1 >> (8 * (lane - 2))) & 0xFFu;
+    else if (lane == 2 + T::ZB) byte = w;
+    else byte = (uint32_t)(flags >> (8 * (nflag - 1 - (lane - 3 - T::ZB)))) & 0xFFu;
+    buf[lane] = (uint8_t)byte;
+  }
+  // zero the slack after the payload so that the aligned reads below see
+  // defined bytes
+  if (lane < 8) reinterpret_cast<uint32_t*>(buf)[((S + 3) >> 2) + lane] = 0u;
+
+  // a10 (first half): publish the chunk size, read the in-group window
+  const uint64_t sample = lookback_begin(status, t, c, S, epoch, lane);
   wave_lds_sync();
-  {
-    const uint32_t total = pad + S;
-    uint8_t* dal = dst - pad;
-    const uint32_t nblk = (total + 15) >> 4;
-    for (uint32_t i = lane; i < nblk; i += 64) {
-      const uint32_t b_lo = i << 4, b_hi = b_lo + 16;
-      if (b_lo >= pad && b_hi <= total) {
-        *reinterpret_cast<uint4*>(dal + b_lo) = *reinterpret_cast<const uint4*>(buf + b_lo);
+
+  // a10 (second half): exclusive prefix of the chunk sizes
+  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, sample);
+
+  // a11 (second half): copy the payload to payload + off with aligned
+  // 16-byte stores; byte stores only in the first and last block.
+  uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
+  const uint32_t ph = (uint32_t)((uintptr_t)dst & 15u);
+  uint8_t* dal = dst - ph;
+  const uint32_t nblk = (ph + S + 15) >> 4;
+  const uint32_t r8 = 8 * ((16u - ph) & 3u);       // byte shift inside a dword, as bits
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(buf);
+  for (uint32_t k = lane; k < nblk; k += 64) {
+    const bool edge = (k == 0 && ph != 0) || (16 * k + 16 > ph + S);
+    if (!edge) {
+      // payload bytes [16k - ph, 16k - ph + 16) from dwords starting at q
+      const uint32_t q = (16 * k - ph) >> 2;
+      const uint32_t d0 = bw[q], d1 = bw[q + 1], d2 = bw[q + 2], d3 = bw[q + 3], d4 = bw[q + 4];
+      uint4 v;
+      if (r8 == 0) {
+        v = make_uint4(d0, d1, d2, d3);
       } else {
-        const uint32_t from = b_lo > pad ? b_lo : pad, to = b_hi < total ? b_hi : total;
-        for (uint32_t b = from; b < to; ++b) dal[b] = buf[b];
+        v.x = __builtin_amdgcn_alignbyte(d1, d0, r8 >> 3);
+        v.y = __builtin_amdgcn_alignbyte(d2, d1, r8 >> 3);
+        v.z = __builtin_amdgcn_alignbyte(d3, d2, r8 >> 3);
+        v.w = __builtin_amdgcn_alignbyte(d4, d3, r8 >> 3);
       }
+      *reinterpret_cast<uint4*>(dal + 16 * k) = v;
+    } else {
+      const uint32_t from = 16 * k > ph ? 16 * k : ph;
+      const uint32_t to = 16 * k + 16 < ph + S ? 16 * k + 16 : ph + S;
+      for (uint32_t b = from; b < to; ++b) dal[b] = buf[b - ph];
     }
   }
   if (lane == 0) reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = S;
@@ -427,18 +444,21 @@ __device__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressS
 // Decompression of one chunk (Sec. 4, executed by one wave)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const DecompressSeries& sd, uint64_t c,
-                                 uint64_t nc, uint64_t tglob, uint64_t* status, uint32_t epoch, int lane,
-                                 Ctl* ctl) {
+__device__ __forceinline__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const DecompressSeries& sd,
+                                                 uint64_t c, uint64_t nc, uint64_t t, uint64_t* status,
+                                                 uint64_t* gstatus, uint32_t epoch, int lane_in, Ctl* ctl) {
   using U = typename T::U;
   using F = typename T::F;
   using S_ = typename T::S;
+  int lane = lane_in;  // opaque, see compress_chunk
+  asm volatile("" : "+v"(lane));
   const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
   const uint32_t S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
   bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB);
   const uint64_t agg = bad ? 0 : S;
   // d1: chunk offset = exclusive prefix of the size array (look-back)
-  const uint64_t off = lookback(status, tglob, tglob - c, agg, epoch, lane);
+  const uint64_t sample = lookback_begin(status, t, c, agg, epoch, lane);
+  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, agg, epoch, lane, sample);
   if (off + agg > sd.payload_bytes) bad = true;
   if (c == nc - 1 && off + agg != sd.payload_bytes) bad = true;
   if (bad) {
@@ -447,8 +467,8 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
   }
   // stage the payload bytes in LDS at their 16-byte phase
   const uint8_t* src = payload + off;
-  const uint32_t pad = (uint32_t)((uintptr_t)src & 15u);
-  const uint32_t total = pad + S;
+  const uint32_t pad = uniform((uint32_t)((uintptr_t)src & 15u));
+  const uint32_t total = uniform(pad + S);
   {
     const uint8_t* sal = src - pad;
     const uint32_t nblk = (total + 15) >> 4;
@@ -483,10 +503,11 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
   uint32_t lo[16], hi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) lo[i] = hi[i] = 0;
-  uint32_t cur = pad + 3 + T::ZB + nflag;
+  uint32_t cur = uniform(pad + 3 + T::ZB + nflag);
   const int q = lane >> 2, u2 = 2 * (lane & 3);
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
+    cur = uniform(cur);
     if (!bad && p < (int)w) {
       uint32_t fld = 0;
       if ((flags >> p) & 1) {
@@ -503,10 +524,12 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
         const uint32_t a0 = cur & ~3u, sh = (cur & 3u) * 8;
         const uint32_t* d = reinterpret_cast<const uint32_t*>(buf + a0);
         const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-        const uint32_t m0 = sh ? (d0 >> sh) | (d1 << (32 - sh)) : d0;
-        const uint32_t m1 = sh ? (d1 >> sh) | (d2 << (32 - sh)) : d1;
-        const uint32_t m2 = sh ? (d2 >> sh) | (d3 << (32 - sh)) : d2;
-        const uint32_t m3 = sh ? (d3 >> sh) | (d4 << (32 - sh)) : d3;
+        // every lane read the same bytes: make the bitmap wave-uniform so
+        // that the row cursor stays a scalar
+        const uint32_t m0 = uniform(sh ? (d0 >> sh) | (d1 << (32 - sh)) : d0);
+        const uint32_t m1 = uniform(sh ? (d1 >> sh) | (d2 << (32 - sh)) : d1);
+        const uint32_t m2 = uniform(sh ? (d2 >> sh) | (d3 << (32 - sh)) : d2);
+        const uint32_t m3 = uniform(sh ? (d3 >> sh) | (d4 << (32 - sh)) : d3);
         const uint32_t p0 = __popc(m0), p1 = __popc(m1), p2 = __popc(m2), p3 = __popc(m3);
         const uint32_t nnz = p0 + p1 + p2 + p3;
         if (cur + 16 + nnz > total) {
@@ -519,8 +542,10 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
           const uint32_t byteq = (md >> (8 * bi)) & 0xFFu;
           const uint32_t nz0 = (byteq >> (7 - u2)) & 1u, nz1 = (byteq >> (6 - u2)) & 1u;
           const uint32_t rank = before + (uint32_t)__popc(byteq >> (8 - u2));
-          const uint32_t b0 = nz0 ? buf[cur + 16 + rank] : 0u;
-          const uint32_t b1 = nz1 ? buf[cur + 16 + rank + nz0] : 0u;
+          // both reads stay inside the row's data bytes or the buffer slack
+          const uint32_t r0 = buf[cur + 16 + rank], r1 = buf[cur + 16 + rank + nz0];
+          const uint32_t b0 = nz0 ? r0 : 0u;
+          const uint32_t b1 = nz1 ? r1 : 0u;
           fld = b0 | (b1 << 8);
           cur += 16 + nnz;
         }
@@ -541,12 +566,12 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
   U gv[16];
   U run = 0;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int i = 0; i < 16; ++i) {
     U et;
-    if constexpr (sizeof(U) == 8) et = ((uint64_t)hi[t ^ 7] << 32) | lo[t ^ 7];
-    else et = lo[t ^ 7];
+    if constexpr (sizeof(U) == 8) et = ((uint64_t)hi[i ^ 7] << 32) | lo[i ^ 7];
+    else et = lo[i ^ 7];
     run += unzigzag<U>(et);
-    gv[t] = run;
+    gv[i] = run;
   }
   const uint64_t incl = wave_incl_scan64((uint64_t)run, lane);
   const U basev = (U)(z1 + (U)(incl - (uint64_t)run));
@@ -556,11 +581,11 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
   wave_lds_sync();
   U* vals = reinterpret_cast<U*>(buf);
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const U gt = (U)(basev + gv[t]);
+  for (int i = 0; i < 16; ++i) {
+    const U gt = (U)(basev + gv[i]);
     const U bits = case1 ? T::u((F)(S_)gt / P) : unzigzag<U>(gt);
-    const uint32_t i = 16u * lane + 1 + t;
-    vals[i + (i >> 4)] = bits;
+    const uint32_t idx = 16u * lane + 1 + i;
+    vals[idx + (idx >> 4)] = bits;
   }
   const U v1 = case1 ? T::u((F)(S_)z1 / P) : unzigzag<U>(z1);
   wave_lds_sync();
@@ -578,11 +603,10 @@ __device__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const Decompr
 }
 
 // ---------------------------------------------------------------------------
-// Kernels
+// Kernels (one instantiation per dtype; a launch carries series of one dtype)
 // ---------------------------------------------------------------------------
 template <class Series>
-__device__ __forceinline__ const Series& find_series(const Series& one, const Series* many, uint32_t ns,
-                                                     uint64_t t, Series& tmp) {
+__device__ __forceinline__ Series find_series(const Series& one, const Series* many, uint32_t ns, uint64_t t) {
   if (ns <= 1) return one;
   uint32_t lo = 0, hi = ns - 1;  // last series with chunk0 <= t
   while (lo < hi) {
@@ -590,8 +614,7 @@ __device__ __forceinline__ const Series& find_series(const Series& one, const Se
     if (many[mid].chunk0 <= t) lo = mid;
     else hi = mid - 1;
   }
-  tmp = many[lo];
-  return tmp;
+  return many[lo];
 }
 
 __device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, int lane) {
@@ -604,7 +627,8 @@ __device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, in
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compress(CompressArgs a) {
+template <class T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
   __shared__ BlockLds sm;
   load_tables(sm);
   __syncthreads();
@@ -618,17 +642,16 @@ __global__ __launch_bounds__(kBlock) void k_compress(CompressArgs a) {
       if (t == 0 && a.nseries == 1) write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
       break;
     }
-    CompressSeries tmp;
-    const CompressSeries& sd = find_series(a.one, a.many, a.nseries, t, tmp);
+    const CompressSeries sd = find_series(a.one, a.many, a.nseries, t);
     const uint64_t c = t - sd.chunk0;
     const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    if (sd.dtype == 2) compress_chunk<TF64>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane);
-    else compress_chunk<TF32>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane);
+    compress_chunk<T>(sm, buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane);
   }
   exit_protocol(a.ctl, a.total_waves, lane);
 }
 
-__global__ __launch_bounds__(kBlock) void k_decompress(DecompressArgs a) {
+template <class T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
   __shared__ BlockLds sm;
   load_tables(sm);
   __syncthreads();
@@ -639,12 +662,10 @@ __global__ __launch_bounds__(kBlock) void k_decompress(DecompressArgs a) {
     if (lane == 0) t = atomicAdd(&a.ctl->ticket, 1u);
     t = uniform(t);
     if (t >= a.total_chunks) break;
-    DecompressSeries tmp;
-    const DecompressSeries& sd = find_series(a.one, a.many, a.nseries, t, tmp);
+    const DecompressSeries sd = find_series(a.one, a.many, a.nseries, t);
     const uint64_t c = t - sd.chunk0;
     const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    if (sd.dtype == 2) decompress_chunk<TF64>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
-    else decompress_chunk<TF32>(sm, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
+    decompress_chunk<T>(sm, buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane, a.ctl);
   }
   exit_protocol(a.ctl, a.total_waves, lane);
 }
@@ -654,12 +675,14 @@ __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
     p[i] = v;
 }
 
-hipError_t launch_compress(const CompressArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_compress, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s) {
+  if (dtype == 2) hipLaunchKernelGGL(k_compress<TF64>, dim3(grid), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_compress<TF32>, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_decompress(const DecompressArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_decompress, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s) {
+  if (dtype == 2) hipLaunchKernelGGL(k_decompress<TF64>, dim3(grid), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_decompress<TF32>, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
@@ -678,9 +701,13 @@ static int max_grid_of(const void* fn, int device) {
     per_cu = 1;
   return per_cu * prop.multiProcessorCount;
 }
-int max_grid_compress(int device) { return max_grid_of(reinterpret_cast<const void*>(&k_compress), device); }
-int max_grid_decompress(int device) {
-  return max_grid_of(reinterpret_cast<const void*>(&k_decompress), device);
+int max_grid_compress(int device, int dtype) {
+  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_compress<TF64>), device)
+                    : max_grid_of(reinterpret_cast<const void*>(&k_compress<TF32>), device);
+}
+int max_grid_decompress(int device, int dtype) {
+  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF64>), device)
+                    : max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF32>), device);
 }
 
 }  // namespace falcon_dev

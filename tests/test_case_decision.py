@@ -1,7 +1,9 @@
 """The GPU decides a chunk's case (Eq. 3) without running Alg. 2 value by
-value: it tests every value once at the chunk's largest admissible scale
-L* = min(AMAX, BMAX - 1 - FL10(v_max)), bisects alpha_max below it, and
-checks a failing value at its own limit (see decide_case in kernels.hip).
+value: it applies the stopping test to every value once at the chunk's
+largest admissible scale L* = min(AMAX, BMAX - 1 - FL10(v_max)), bisects
+alpha_max below it with the stopping test, applies the recover check once
+at the result, and checks a value failing at L* at its own limit (see
+decide_case in kernels.hip).
 This test restates that procedure with numpy, independently of the HIP
 code, and checks that on adversarial chunks it reaches the header (A, B)
 the oracle's literal Alg. 2 gives.  Chunks the procedure hands to the
@@ -68,7 +70,8 @@ def fast_decide(spec, v):
         return 0, 0
     maxfl = int(spec.fl10(np.array([vmax], spec.U))[0])
     lstar = min(spec.A, spec.B - 1 - maxfl)
-    fail = ~spec.full(v, spec.P[lstar])
+    ok_l, _ = spec.eps(v, spec.P[lstar])
+    fail = ~ok_l
     if not fail.any():
         a, h = 0, lstar
         while a < h:
@@ -78,7 +81,7 @@ def fast_decide(spec, v):
                 h = mid
             else:
                 a = mid + 1
-        if h != lstar and not spec.full(v, spec.P[h]).all():
+        if not spec.full(v, spec.P[h]).all():
             return None
         return h, h + maxfl + 1
     fl = spec.fl10(m[fail])
