@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 28, help="values (default: the 2 GiB workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain device copy of the input "
+                         "(2 GiB read + 2 GiB write) as the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this codec's multi-GPU "
@@ -132,6 +135,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert torch.equal(ybuf.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
+    if args.copy_calibration:
+        ybuf.copy_(xd)
+        torch.cuda.synchronize()
 
     clen = s.numel()
     ratio = clen / nbytes

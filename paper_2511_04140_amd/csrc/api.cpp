@@ -79,8 +79,8 @@ falcon_status prepare_launch(falcon_ctx* ctx, uint64_t nchunks, uint64_t ngroups
 
 uint64_t groups_of(uint64_t nchunks) { return (nchunks + 63) / 64; }
 
-int grid_for(int max_grid, uint64_t nchunks) {
-  uint64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+int grid_for(int max_grid, uint64_t nchunks, int waves_per_block) {
+  uint64_t want = (nchunks + waves_per_block - 1) / waves_per_block;
   if (want < 1) want = 1;
   return (int)(want < (uint64_t)max_grid ? want : (uint64_t)max_grid);
 }
@@ -184,8 +184,8 @@ falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falco
   a.gstatus = ctx->gstatus;
   a.ctl = ctx->ctl;
   a.epoch = ctx->epoch;
-  const int grid = grid_for(ctx->grid_c[dt], nc);
-  a.total_waves = (uint32_t)(grid * kWavesPerBlock);
+  const int grid = grid_for(ctx->grid_c[dt], nc, kCompressWaves);
+  a.total_waves = (uint32_t)(grid * kCompressWaves);
   ctx->timed = false;
   if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   if ((st = dev_err(launch_compress(a, (int)dt, grid, s))) != FALCON_OK) return st;
@@ -220,7 +220,17 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
   if (out_cap_bytes / es < n) return FALCON_ERR_BUFFER_TOO_SMALL;
   if (n == 0) return payload == 0 ? FALCON_OK : FALCON_ERR_CORRUPT_STREAM;
   if (!d_out || ((uintptr_t)d_out % es)) return FALCON_ERR_INVALID_ARG;
-  if ((st = prepare_launch(ctx, nc, groups_of(nc) + 1, s)) != FALCON_OK) return st;
+  if ((st = prepare_launch(ctx, nc, groups_of(nc) + scan_tiles(nc) + 1, s)) != FALCON_OK) return st;
+  // chunk offsets: exclusive prefix of the size array, written into the
+  // status array (offsets carry a zero epoch tag, so a later compression
+  // never mistakes them for look-back words); the tile sums go to gstatus.
+  const uint32_t lo = dt == FALCON_FLOAT64 ? 11u : 7u;
+  const uint32_t hi = (uint32_t)(dt == FALCON_FLOAT64 ? kF64Chunk : kF32Chunk);
+  ctx->timed = false;
+  if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(d_in) + 32), nc,
+                                      lo, hi, payload, ctx->gstatus, ctx->status, ctx->ctl, ctx->epoch, s))) !=
+      FALCON_OK)
+    return st;
   DecompressArgs a{};
   a.one.in = static_cast<const uint8_t*>(d_in);
   a.one.out = static_cast<uint8_t*>(d_out);
@@ -233,12 +243,10 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
   a.nseries = 1;
   a.total_chunks = nc;
   a.status = ctx->status;
-  a.gstatus = ctx->gstatus;
   a.ctl = ctx->ctl;
   a.epoch = ctx->epoch;
-  const int grid = grid_for(ctx->grid_d[dt], nc);
-  a.total_waves = (uint32_t)(grid * kWavesPerBlock);
-  ctx->timed = false;
+  const int grid = grid_for(ctx->grid_d[dt], nc, kDecompressWaves);
+  a.total_waves = (uint32_t)(grid * kDecompressWaves);
   if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   if ((st = dev_err(launch_decompress(a, (int)dt, grid, s))) != FALCON_OK) return st;
   if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;

@@ -25,8 +25,8 @@
 namespace falcon_dev {
 
 constexpr int kChunk = 1025;      // values per chunk (Sec. 5.1.4, n = 64k + 1)
-constexpr int kWaves = 4;         // wavefronts per workgroup
-constexpr int kBlock = 64 * kWaves;
+constexpr int kWavesC = 16;       // wavefronts per compression workgroup
+constexpr int kWavesD = 4;        // wavefronts per decompression workgroup
 constexpr int kGSlots = kChunk + 65;         // skewed slots: one pad every 16
 constexpr int kWaveLds = kGSlots * 8;        // 8720 bytes per wave
 constexpr int kHdrBytes = 32;
@@ -56,14 +56,23 @@ __constant__ float c_pow10_f32[21] = {
     0x1.2a05f2p+33f};
 
 // Shared memory of one workgroup: the power tables (copied once per block so
-// that per-lane lookups are LDS reads) and one byte buffer per wavefront.
-struct __attribute__((aligned(16))) BlockLds {
+// that per-lane lookups are LDS reads), the chunk-ticket ring of the
+// compression kernel, and one byte buffer per wavefront.
+struct __attribute__((aligned(16))) LdsTables {
   double p64[48];
   float p32[24];
-  uint4 wave[kWaves][kWaveLds / 16];
+};
+template <int NW>
+struct __attribute__((aligned(16))) BlockLdsT {
+  LdsTables tab;
+  uint32_t slot_next;     // next ticket slot of this workgroup
+  uint32_t ring_round[8]; // round whose batch index sits in ring_batch
+  uint32_t ring_batch[8];
+  uint32_t pad[3];
+  uint4 wave[NW][kWaveLds / 16];
 };
 
-__device__ __forceinline__ void load_tables(BlockLds& s) {
+__device__ __forceinline__ void load_tables(LdsTables& s) {
   for (int i = threadIdx.x; i < 45; i += blockDim.x) s.p64[i] = c_pow10_f64[i];
   for (int i = threadIdx.x; i < 21; i += blockDim.x) s.p32[i] = c_pow10_f32[i];
 }
@@ -97,7 +106,7 @@ struct TF64 {
     F t = r + 6755399441055744.0;
     return (S)(u(t) - 0x4338000000000000ull);
   }
-  static __device__ __forceinline__ F pow10(const BlockLds& s, int k) { return s.p64[k + POFF]; }
+  static __device__ __forceinline__ F pow10(const LdsTables& s, int k) { return s.p64[k + POFF]; }
 };
 
 struct TF32 {
@@ -122,7 +131,7 @@ struct TF32 {
     F t = r + 12582912.0f;  // 1.5 * 2^23, exact for |r| < 2^22
     return (S)(u(t) - 0x4B400000u);
   }
-  static __device__ __forceinline__ F pow10(const BlockLds& s, int k) { return s.p32[k + POFF]; }
+  static __device__ __forceinline__ F pow10(const LdsTables& s, int k) { return s.p32[k + POFF]; }
 };
 
 // Zigzag of Eq. 4: (x << 1) xor (x >> (W-1)), arithmetic shift.
@@ -293,24 +302,32 @@ __device__ __forceinline__ bool window_sum(uint64_t s, bool valid, uint32_t epoc
   return true;
 }
 
-struct LookbackState {
-  uint64_t first_sample;  // status of chunk t-1-lane, loaded early
+struct LookbackSamples {
+  uint64_t intra;  // status of chunk t-1-lane (lanes below the in-group position)
+  uint64_t group;  // status of group g-1-lane
 };
 
-// Publishes the chunk aggregate and issues the load of the in-group window.
-// c is the chunk's index in its series, t its status index.
-__device__ __forceinline__ uint64_t lookback_begin(uint64_t* status, uint64_t t, uint64_t c, uint64_t agg,
-                                                   uint32_t epoch, int lane) {
+// Publishes the chunk aggregate and issues the loads of both windows (the
+// chunks before it in its group, and the 64 groups before its group), so
+// that their latencies overlap with each other and with the caller's work.
+// c is the chunk's index in its series, t its status index, gbase the index
+// of the series' first group word.
+__device__ __forceinline__ LookbackSamples lookback_begin(uint64_t* status, uint64_t* gstatus, uint64_t t,
+                                                          uint64_t c, uint64_t gbase, uint64_t agg,
+                                                          uint32_t epoch, int lane) {
   const uint32_t j = (uint32_t)(c & 63);
+  const int64_t g = (int64_t)(c >> 6);
   if (lane == 0) status_store(status + t, status_word(epoch, c == 0 ? kFlagPrefix : kFlagAgg, agg));
-  return (lane < (int)j) ? status_load(status + t - 1 - lane) : 0;
+  LookbackSamples smp;
+  smp.intra = (lane < (int)j) ? status_load(status + t - 1 - lane) : 0;
+  smp.group = (g - 1 - lane >= 0) ? status_load(gstatus + gbase + (g - 1 - lane)) : 0;
+  return smp;
 }
 
-// Completes the look-back; returns the chunk's exclusive prefix.  gstatus is
-// the group status array, gbase the index of the series' first group.
+// Completes the look-back; returns the chunk's exclusive prefix.
 __device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gstatus, uint64_t t, uint64_t c,
                                                  uint64_t gbase, uint64_t agg, uint32_t epoch, int lane,
-                                                 uint64_t sample) {
+                                                 LookbackSamples smp) {
   if (c == 0) return 0;  // the prefix word was published by lookback_begin
   const uint32_t j = (uint32_t)(c & 63);
   const uint64_t g = c >> 6;
@@ -318,6 +335,7 @@ __device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gst
   bool found = false;
   if (j > 0) {
     const bool valid = lane < (int)j;
+    uint64_t sample = smp.intra;
     while (!window_sum(sample, valid, epoch, intra, found)) {
       __builtin_amdgcn_s_sleep(1);
       sample = valid ? status_load(status + t - 1 - lane) : 0;
@@ -330,10 +348,10 @@ __device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gst
     if (j == 63 && lane == 0) status_store(gstatus + gbase + g, status_word(epoch, kFlagAgg, intra + agg));
     uint64_t gx = 0;
     int64_t k = (int64_t)g - 1;  // nearest group first
+    uint64_t s = smp.group;
     while (k >= 0) {
       const int64_t idx = k - lane;
       const bool valid = idx >= 0;
-      uint64_t s = valid ? status_load(gstatus + gbase + idx) : 0;
       uint64_t part;
       bool gfound;
       while (!window_sum(s, valid, epoch, part, gfound)) {
@@ -343,6 +361,7 @@ __device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gst
       gx += part;
       if (gfound) break;
       k -= 64;
+      s = (k - lane >= 0) ? status_load(gstatus + gbase + (k - lane)) : 0;
     }
     excl = gx + intra;
   }
@@ -354,7 +373,8 @@ __device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gst
 }
 
 // Byte access into a wave's LDS buffer.
-__device__ __forceinline__ uint8_t* wave_bytes(BlockLds& s, int wid) {
+template <int NW>
+__device__ __forceinline__ uint8_t* wave_bytes(BlockLdsT<NW>& s, int wid) {
   return reinterpret_cast<uint8_t*>(&s.wave[wid][0]);
 }
 

@@ -60,19 +60,24 @@ struct DecompressArgs {
   uint32_t nseries;
   uint32_t total_waves;
   uint64_t total_chunks;
-  uint64_t* status;    // one word per chunk of the launch
-  uint64_t* gstatus;   // one word per 64-chunk group of each series
+  const uint64_t* status;  // chunk offsets (exclusive prefix of the sizes)
   Ctl* ctl;
   uint32_t epoch;
   uint32_t pad;
 };
 
-constexpr int kThreadsPerBlock = 256;
-constexpr int kWavesPerBlock = 4;
+constexpr int kCompressWaves = 16;    // wavefronts per compression workgroup
+constexpr int kDecompressWaves = 4;   // wavefronts per decompression workgroup
 
 hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+// Exclusive prefix of n chunk sizes into offsets; sizes outside [lo, hi] or
+// a total other than expect store the epoch in ctl->error.  tile_tmp holds
+// scan_tiles(n) words.
+hipError_t launch_scan_sizes(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi, uint64_t expect,
+                             uint64_t* tile_tmp, uint64_t* offsets, Ctl* ctl, uint32_t epoch, hipStream_t s);
+uint64_t scan_tiles(uint64_t n);
 // Largest number of co-resident workgroups of each kernel on the device.
 int max_grid_compress(int device, int dtype);
 int max_grid_decompress(int device, int dtype);

@@ -23,7 +23,7 @@ namespace falcon_dev {
 // gives k0 with fl(10^k0) <= 2^e2 <= |v| < 2^(e2+1) <= fl(10^(k0+2)), so the
 // answer is k0 or k0 + 1.
 template <class T>
-__device__ __forceinline__ int fl10(const BlockLds& sm, typename T::U mag) {
+__device__ __forceinline__ int fl10(const LdsTables& sm, typename T::U mag) {
   const int e2 = T::expf(mag) - T::BIAS;
   const int k0 = (e2 * 78913) >> 18;
   return k0 + (mag >= T::u(T::pow10(sm, k0 + 1)) ? 1 : 0);
@@ -62,7 +62,7 @@ __device__ __forceinline__ void set_bit(uint32_t& m, bool c, int k) {
 // cannot settle the chunk.  Returns true if some value is an exception;
 // otherwise amax gets the lane's largest decimal place.
 template <class T>
-__device__ __forceinline__ bool alg2_literal(const BlockLds& sm, const typename T::U (&vb)[17], int& amax) {
+__device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename T::U (&vb)[17], int& amax) {
   bool exc = false;
   amax = 0;
   for (int k = 0; k < 17; ++k) {
@@ -114,7 +114,7 @@ __device__ __forceinline__ bool alg2_literal(const BlockLds& sm, const typename 
 //  4. Anything else (no exception found, alpha_max > L*, i.e. Case 2 with a
 //     real header) runs the literal Alg. 2.
 template <class T>
-__device__ __forceinline__ void decide_case(const BlockLds& sm, const typename T::U (&vb)[17], int& A, int& B,
+__device__ __forceinline__ void decide_case(const LdsTables& sm, const typename T::U (&vb)[17], int& A, int& B,
                             bool& case1) {
   using U = typename T::U;
   using F = typename T::F;
@@ -254,27 +254,19 @@ __device__ __forceinline__ void write_stream_header(uint8_t* out, uint32_t dtype
 }
 
 // ---------------------------------------------------------------------------
-// Compression of one chunk (Alg. 3 for one chunk, executed by one wave)
+// Compression of one chunk (Alg. 3 for one chunk, executed by one wave).
+// Split in two halves: transform (front) and encode + write (back).
 // ---------------------------------------------------------------------------
+// a1: coalesced load in the slot layout; positions past the end repeat the
+// last value (padding of a partial last chunk).
 template <class T>
-__device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf, const CompressSeries& sd,
-                                               uint64_t c, uint64_t nc, uint64_t t, uint64_t* status,
-                                               uint64_t* gstatus, uint32_t epoch, int lane_in) {
+__device__ __forceinline__ void load_chunk(const CompressSeries& sd, uint64_t c, int lane,
+                                           typename T::U (&vb)[17]) {
   using U = typename T::U;
-  using F = typename T::F;
-  // An opaque copy of the lane index keeps the compiler from hoisting the
-  // per-lane address arithmetic out of the ticket loop, where it would stay
-  // live (and spill) across every chunk.
-  int lane = lane_in;
-  asm volatile("" : "+v"(lane));
   const U* in = reinterpret_cast<const U*>(sd.in);
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
   const uint32_t nv = rem < (uint64_t)kChunk ? (uint32_t)rem : (uint32_t)kChunk;
-
-  // a1: coalesced load, slot layout; positions past the end repeat the last
-  // value (padding of a partial last chunk).
-  U vb[17];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     uint32_t idx = 1 + 64 * k + lane;
@@ -282,16 +274,35 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
     vb[k] = __builtin_nontemporal_load(in + base + idx);
   }
   vb[16] = in[base];
+}
 
-  // a2-a3: decimal places and the chunk case
+struct ChunkPlanes {
+  uint32_t lo[16], hi[16];  // bit planes after the transpose (see plane_field)
+  uint64_t z1;
   int A, B;
+  uint32_t w;
+};
+
+// a2-a7: decimal places and case, Eq. 3 and Eq. 4, bit width, transpose.
+// vb is consumed (free for the next chunk's loads when this returns).
+template <class T>
+__device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
+                                               int lane_in, ChunkPlanes& cp) {
+  using U = typename T::U;
+  using F = typename T::F;
+  // An opaque copy of the lane index keeps the compiler from hoisting the
+  // per-lane address arithmetic out of the ticket loop, where it would stay
+  // live (and spill) across every chunk.
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
+
   bool case1;
-  decide_case<T>(sm, vb, A, B, case1);
+  decide_case<T>(sm, vb, cp.A, cp.B, case1);
 
   // a4: Eq. 3 -> g, written to LDS in skewed natural order
   U* g = reinterpret_cast<U*>(buf);
   {
-    const F P = T::pow10(sm, case1 ? A : 0);
+    const F P = T::pow10(sm, case1 ? cp.A : 0);
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
       U gk;
@@ -312,9 +323,8 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
   }
   wave_lds_sync();
 
-  // a5: Eq. 4 in the contiguous layout: e[t] = z_{16L+t+2}
+  // a5: Eq. 4 in the contiguous layout: e[q] = z_{16L+q+2}
   U e[16];
-  U z1;
   {
     const uint32_t b0 = 17u * lane;
     U prev = g[b0];
@@ -324,7 +334,7 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
       e[q] = zigzag<U>((U)(cur - prev));
       prev = cur;
     }
-    z1 = g[0];
+    cp.z1 = (uint64_t)g[0];
   }
   wave_lds_sync();
 
@@ -332,46 +342,78 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
   U orv = 0;
 #pragma unroll
   for (int q = 0; q < 16; ++q) orv |= e[q];
-  uint32_t w;
   if constexpr (sizeof(U) == 8) {
     const uint64_t o = uniform64(wave_or64((uint64_t)orv));
-    w = o ? 64u - (uint32_t)__builtin_clzll(o) : 0u;
+    cp.w = o ? 64u - (uint32_t)__builtin_clzll(o) : 0u;
   } else {
     const uint32_t o = uniform(wave_or32((uint32_t)orv));
-    w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
+    cp.w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
   }
 
   // a7: bit-plane transpose; element q of the lane goes to row q ^ 7 so that
   // the first element of each byte lands in its most significant bit.
-  uint32_t lo[16], hi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    lo[i] = (uint32_t)e[i ^ 7];
-    hi[i] = sizeof(U) == 8 ? (uint32_t)((uint64_t)e[i ^ 7] >> 32) : 0u;
+    cp.lo[i] = (uint32_t)e[i ^ 7];
+    cp.hi[i] = sizeof(U) == 8 ? (uint32_t)((uint64_t)e[i ^ 7] >> 32) : 0u;
   }
-  xpose16(lo);
-  if constexpr (sizeof(U) == 8) xpose16(hi);
+  xpose16(cp.lo);
+  if constexpr (sizeof(U) == 8) xpose16(cp.hi);
+}
 
-  // a8-a9 and the first half of a11, in one pass over the planes: count the
-  // row's zero bytes, choose its scheme (sparse iff more than 16 of its 128
-  // bytes are zero; ties dense), and write it to LDS after the chunk header.
+// a8-a11: row schemes and sizes, look-back, payload assembly and write-out.
+template <class T>
+__device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries& sd, uint64_t c, uint64_t nc,
+                                              uint64_t t, uint64_t* status, uint64_t* gstatus, uint32_t epoch,
+                                              int lane_in, const ChunkPlanes& cp) {
+  int lane = lane_in;  // opaque, see compress_front
+  asm volatile("" : "+v"(lane));
+  const uint32_t w = cp.w;
+  // a8-a9: per-row non-zero byte counts (sparse iff more than 16 of the 128
+  // bytes are zero; ties dense), scheme flags and the chunk size.
+  uint64_t flags = 0;
+  uint32_t rows = 0;
+  for_planes_down<T::W - 1>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p < (int)w) {
+      const uint32_t fld = plane_field<T, p>(cp.lo, cp.hi);
+      const uint64_t E = ballot((fld & 0xFFu) != 0), O = ballot((fld & 0xFF00u) != 0);
+      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+      const bool dense = nnz >= 112;
+      flags |= (uint64_t)dense << p;
+      rows += dense ? 128u : 16u + nnz;
+    }
+  });
   const uint32_t nflag = (w + 7) >> 3;
   const uint32_t hlen = 3 + T::ZB + nflag;
-  uint64_t flags = 0;
+  const uint32_t S = hlen + rows;
+
+  // a10 (first half): publish the chunk size and issue the look-back reads
+  const LookbackSamples smp = lookback_begin(status, gstatus, t, c, sd.group0, S, epoch, lane);
+
+  // a11 (first half): assemble the payload in LDS at offset 0 while the
+  // look-back reads are in flight.
+  if (lane < (int)hlen) {
+    uint32_t byte;
+    if (lane == 0) byte = (uint32_t)cp.A;
+    else if (lane == 1) byte = (uint32_t)cp.B;
+    else if (lane < 2 + T::ZB) byte = (uint32_t)(cp.z1 >> (8 * (lane - 2))) & 0xFFu;
+    else if (lane == 2 + T::ZB) byte = w;
+    else byte = (uint32_t)(flags >> (8 * (nflag - 1 - (lane - 3 - T::ZB)))) & 0xFFu;
+    buf[lane] = (uint8_t)byte;
+  }
   uint32_t cur = hlen;
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
     if (p < (int)w) {
-      const uint32_t fld = plane_field<T, p>(lo, hi);
+      const uint32_t fld = plane_field<T, p>(cp.lo, cp.hi);
       const uint32_t b0 = fld & 0xFFu, b1 = fld >> 8;
-      const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
-      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
-      if (nnz >= 112) {
-        flags |= 1ull << p;
+      if ((flags >> p) & 1) {
         buf[cur + 2 * lane] = (uint8_t)b0;
         buf[cur + 2 * lane + 1] = (uint8_t)b1;
         cur += 128;
       } else {
+        const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
         // bitmap byte q covers row bytes 8q..8q+7, i.e. lanes 4q..4q+3
         uint32_t bits = (((b0 != 0) ? 2u : 0u) | ((b1 != 0) ? 1u : 0u)) << (6 - 2 * (lane & 3));
         bits |= shfl_xor32(bits, 1);
@@ -380,30 +422,17 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
         const uint32_t rank = mbcnt(E) + mbcnt(O);
         if (b0) buf[cur + 16 + rank] = (uint8_t)b0;
         if (b1) buf[cur + 16 + rank + (b0 ? 1 : 0)] = (uint8_t)b1;
-        cur += 16u + nnz;
+        cur += 16u + (uint32_t)(__popcll(E) + __popcll(O));
       }
     }
   });
-  const uint32_t S = cur;
-  if (lane < (int)hlen) {
-    uint32_t byte;
-    if (lane == 0) byte = (uint32_t)A;
-    else if (lane == 1) byte = (uint32_t)B;
-    else if (lane < 2 + T::ZB) byte = (uint32_t)((uint64_t)z1 >> (8 * (lane - 2))) & 0xFFu;
-    else if (lane == 2 + T::ZB) byte = w;
-    else byte = (uint32_t)(flags >> (8 * (nflag - 1 - (lane - 3 - T::ZB)))) & 0xFFu;
-    buf[lane] = (uint8_t)byte;
-  }
   // zero the slack after the payload so that the aligned reads below see
   // defined bytes
   if (lane < 8) reinterpret_cast<uint32_t*>(buf)[((S + 3) >> 2) + lane] = 0u;
-
-  // a10 (first half): publish the chunk size, read the in-group window
-  const uint64_t sample = lookback_begin(status, t, c, S, epoch, lane);
   wave_lds_sync();
 
   // a10 (second half): exclusive prefix of the chunk sizes
-  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, sample);
+  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, smp);
 
   // a11 (second half): copy the payload to payload + off with aligned
   // 16-byte stores; byte stores only in the first and last block.
@@ -411,7 +440,7 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
   const uint32_t ph = (uint32_t)((uintptr_t)dst & 15u);
   uint8_t* dal = dst - ph;
   const uint32_t nblk = (ph + S + 15) >> 4;
-  const uint32_t r8 = 8 * ((16u - ph) & 3u);       // byte shift inside a dword, as bits
+  const uint32_t rb = (16u - ph) & 3u;  // byte shift inside a dword
   const uint32_t* bw = reinterpret_cast<const uint32_t*>(buf);
   for (uint32_t k = lane; k < nblk; k += 64) {
     const bool edge = (k == 0 && ph != 0) || (16 * k + 16 > ph + S);
@@ -420,13 +449,13 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
       const uint32_t q = (16 * k - ph) >> 2;
       const uint32_t d0 = bw[q], d1 = bw[q + 1], d2 = bw[q + 2], d3 = bw[q + 3], d4 = bw[q + 4];
       uint4 v;
-      if (r8 == 0) {
+      if (rb == 0) {
         v = make_uint4(d0, d1, d2, d3);
       } else {
-        v.x = __builtin_amdgcn_alignbyte(d1, d0, r8 >> 3);
-        v.y = __builtin_amdgcn_alignbyte(d2, d1, r8 >> 3);
-        v.z = __builtin_amdgcn_alignbyte(d3, d2, r8 >> 3);
-        v.w = __builtin_amdgcn_alignbyte(d4, d3, r8 >> 3);
+        v.x = __builtin_amdgcn_alignbyte(d1, d0, rb);
+        v.y = __builtin_amdgcn_alignbyte(d2, d1, rb);
+        v.z = __builtin_amdgcn_alignbyte(d3, d2, rb);
+        v.w = __builtin_amdgcn_alignbyte(d4, d3, rb);
       }
       *reinterpret_cast<uint4*>(dal + 16 * k) = v;
     } else {
@@ -444,23 +473,21 @@ __device__ __forceinline__ void compress_chunk(const BlockLds& sm, uint8_t* buf,
 // Decompression of one chunk (Sec. 4, executed by one wave)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void decompress_chunk(const BlockLds& sm, uint8_t* buf, const DecompressSeries& sd,
-                                                 uint64_t c, uint64_t nc, uint64_t t, uint64_t* status,
-                                                 uint64_t* gstatus, uint32_t epoch, int lane_in, Ctl* ctl) {
+__device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* buf, const DecompressSeries& sd,
+                                                 uint64_t c, uint64_t nc, uint64_t t, const uint64_t* offsets,
+                                                 uint32_t epoch, int lane_in, Ctl* ctl) {
   using U = typename T::U;
   using F = typename T::F;
   using S_ = typename T::S;
-  int lane = lane_in;  // opaque, see compress_chunk
+  int lane = lane_in;  // opaque, see compress_front
   asm volatile("" : "+v"(lane));
   const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
   const uint32_t S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
-  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB);
-  const uint64_t agg = bad ? 0 : S;
-  // d1: chunk offset = exclusive prefix of the size array (look-back)
-  const uint64_t sample = lookback_begin(status, t, c, agg, epoch, lane);
-  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, agg, epoch, lane, sample);
-  if (off + agg > sd.payload_bytes) bad = true;
-  if (c == nc - 1 && off + agg != sd.payload_bytes) bad = true;
+  // d1: chunk offset, from the prefix scan of the size array (k_scan_*),
+  // which also checked every size against [3 + ZB, BOUND] and their sum
+  // against the payload byte count.
+  const uint64_t off = uniform64(offsets[t]);
+  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB) || off + S > sd.payload_bytes;
   if (bad) {
     if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -627,47 +654,176 @@ __device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, in
   }
 }
 
+// Chunk tickets of the compression kernel.  Chunks must be handed out in
+// stream order to waves that are running (the look-back waits only on
+// chunks whose owners already exist).  A single global counter serialises at
+// about 11 ns per atomic, so a workgroup takes batches of kWavesC
+// consecutive chunks with one global atomic and deals them to its waves
+// through an LDS slot counter: slot s of the workgroup is chunk
+// kWavesC * batch(s / kWavesC) + s % kWavesC.  The wave holding the first
+// slot of a round fetches the round's batch and posts it in a small LDS
+// ring; the others read it there.
+struct TicketClaim {
+  uint32_t round, pos, batch;
+};
+
+template <int NW>
+__device__ __forceinline__ TicketClaim claim_slot(BlockLdsT<NW>& sm, Ctl* ctl, int lane) {
+  uint32_t s = 0;
+  if (lane == 0) s = atomicAdd(&sm.slot_next, 1u);
+  s = uniform(s);
+  TicketClaim tc;
+  tc.round = s / NW;
+  tc.pos = s % NW;
+  tc.batch = 0;
+  if (tc.pos == 0) {
+    uint32_t b = 0;
+    if (lane == 0) b = atomicAdd(&ctl->ticket, 1u);
+    tc.batch = b;  // resolved (made uniform and posted) in resolve_slot
+  }
+  return tc;
+}
+
+template <int NW>
+__device__ __forceinline__ uint64_t resolve_slot(BlockLdsT<NW>& sm, TicketClaim tc, int lane) {
+  uint32_t b;
+  const uint32_t ri = tc.round & 7u;
+  if (tc.pos == 0) {
+    b = uniform(tc.batch);
+    if (lane == 0) {
+      __hip_atomic_store(&sm.ring_batch[ri], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(&sm.ring_round[ri], tc.round, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  } else {
+    while (__hip_atomic_load(&sm.ring_round[ri], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != tc.round)
+      __builtin_amdgcn_s_sleep(1);
+    b = __hip_atomic_load(&sm.ring_batch[ri], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    b = uniform(b);
+  }
+  return (uint64_t)b * NW + tc.pos;
+}
+
 template <class T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
-  __shared__ BlockLds sm;
-  load_tables(sm);
+__global__ __launch_bounds__(64 * kWavesC) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
+  __shared__ BlockLdsT<kWavesC> sm;
+  load_tables(sm.tab);
+  if (threadIdx.x == 0) sm.slot_next = 0;
+  if (threadIdx.x < 8) sm.ring_round[threadIdx.x] = 0xFFFFFFFFu;
   __syncthreads();
   const int lane = lane_id();
   uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
+  // A chunk is claimed only when the wave is ready to work on it: a claimed
+  // chunk that waited behind another chunk's look-back would delay its own
+  // size, and with it the look-back of every chunk after it.
+  typename T::U vb[17];
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&a.ctl->ticket, 1u);
-    t = uniform(t);
+    const uint64_t t = resolve_slot(sm, claim_slot(sm, a.ctl, lane), lane);
     if (t >= a.total_chunks) {
       if (t == 0 && a.nseries == 1) write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
       break;
     }
     const CompressSeries sd = find_series(a.one, a.many, a.nseries, t);
     const uint64_t c = t - sd.chunk0;
+    load_chunk<T>(sd, c, lane, vb);
+    ChunkPlanes cp;
+    compress_front<T>(sm.tab, buf, vb, lane, cp);
     const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    compress_chunk<T>(sm, buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane);
+    compress_back<T>(buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane, cp);
   }
   exit_protocol(a.ctl, a.total_waves, lane);
 }
 
+// Decompression has no dependence between chunks once the offsets are
+// known, so waves take chunks by static striding and use no counter.
 template <class T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
-  __shared__ BlockLds sm;
-  load_tables(sm);
+__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
+  __shared__ BlockLdsT<kWavesD> sm;
+  load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();
   uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&a.ctl->ticket, 1u);
-    t = uniform(t);
-    if (t >= a.total_chunks) break;
+  const uint64_t w0 = (uint64_t)blockIdx.x * kWavesD + (threadIdx.x >> 6);
+  for (uint64_t t = w0; t < a.total_chunks; t += a.total_waves) {
     const DecompressSeries sd = find_series(a.one, a.many, a.nseries, t);
     const uint64_t c = t - sd.chunk0;
     const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    decompress_chunk<T>(sm, buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane, a.ctl);
+    decompress_chunk<T>(sm.tab, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
   }
-  exit_protocol(a.ctl, a.total_waves, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Prefix sum of a chunk size array into chunk offsets (decompression, Sec. 4:
+// the size array is scanned into the offset array).  Three small kernels over
+// tiles of kScanTile sizes: tile sums, a scan of the tile sums (which also
+// checks the total against the payload byte count), and the per-tile scan.
+// Sizes outside [lo, hi] set the error word.
+// ---------------------------------------------------------------------------
+constexpr int kScanTile = 4096;  // 256 threads x 16 sizes
+
+__device__ __forceinline__ uint64_t block_excl_scan256(uint64_t v, uint64_t* tmp, uint64_t& total) {
+  // tmp: 4 words of LDS (one per wave)
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint64_t incl = wave_incl_scan64(v, lane);
+  if (lane == 63) tmp[wid] = incl;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int i = 0; i < wid; ++i) before += tmp[i];
+  total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+  __syncthreads();
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi,
+                                                    uint64_t* tile_sum, Ctl* ctl, uint32_t epoch) {
+  __shared__ uint64_t tmp[4];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * 16;
+  uint64_t sum = 0;
+  bool bad = false;
+  for (int k = 0; k < 16; ++k) {
+    if (base + k < n) {
+      const uint32_t v = sizes[base + k];
+      bad |= v < lo || v > hi;
+      sum += v;
+    }
+  }
+  if (bad) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t total;
+  block_excl_scan256(sum, tmp, total);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tile_sums(uint64_t* tile_sum, uint64_t ntiles, uint64_t expect,
+                                                        Ctl* ctl, uint32_t epoch) {
+  __shared__ uint64_t tmp[4];
+  uint64_t carry = 0;
+  for (uint64_t b0 = 0; b0 < ntiles; b0 += 256) {
+    const uint64_t i = b0 + threadIdx.x;
+    const uint64_t v = i < ntiles ? tile_sum[i] : 0;
+    uint64_t total;
+    const uint64_t ex = block_excl_scan256(v, tmp, total);
+    if (i < ntiles) tile_sum[i] = carry + ex;  // becomes the tile's offset
+    carry += total;
+  }
+  if (threadIdx.x == 0 && carry != expect)
+    __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* sizes, uint64_t n, const uint64_t* tile_off,
+                                                    uint64_t* offsets) {
+  __shared__ uint64_t tmp[4];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * 16;
+  uint32_t v[16];
+  uint64_t sum = 0;
+  for (int k = 0; k < 16; ++k) {
+    v[k] = base + k < n ? sizes[base + k] : 0u;
+    sum += v[k];
+  }
+  uint64_t total;
+  uint64_t run = tile_off[blockIdx.x] + block_excl_scan256(sum, tmp, total);
+  for (int k = 0; k < 16; ++k) {
+    if (base + k < n) offsets[base + k] = run;
+    run += v[k];
+  }
 }
 
 __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
@@ -676,15 +832,26 @@ __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
 }
 
 hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s) {
-  if (dtype == 2) hipLaunchKernelGGL(k_compress<TF64>, dim3(grid), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_compress<TF32>, dim3(grid), dim3(kBlock), 0, s, a);
+  if (dtype == 2) hipLaunchKernelGGL(k_compress<TF64>, dim3(grid), dim3(64 * kWavesC), 0, s, a);
+  else hipLaunchKernelGGL(k_compress<TF32>, dim3(grid), dim3(64 * kWavesC), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s) {
-  if (dtype == 2) hipLaunchKernelGGL(k_decompress<TF64>, dim3(grid), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_decompress<TF32>, dim3(grid), dim3(kBlock), 0, s, a);
+  if (dtype == 2) hipLaunchKernelGGL(k_decompress<TF64>, dim3(grid), dim3(64 * kWavesD), 0, s, a);
+  else hipLaunchKernelGGL(k_decompress<TF32>, dim3(grid), dim3(64 * kWavesD), 0, s, a);
   return hipGetLastError();
 }
+hipError_t launch_scan_sizes(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi, uint64_t expect,
+                             uint64_t* tile_tmp, uint64_t* offsets, Ctl* ctl, uint32_t epoch, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, sizes, n, lo, hi, tile_tmp, ctl, epoch);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(256), 0, s, tile_tmp, ntiles, expect, ctl, epoch);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, s, sizes, n, tile_tmp, offsets);
+  return hipGetLastError();
+}
+uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 255) / 256;
@@ -693,21 +860,21 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-static int max_grid_of(const void* fn, int device) {
+static int max_grid_of(const void* fn, int device, int block) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   return per_cu * prop.multiProcessorCount;
 }
 int max_grid_compress(int device, int dtype) {
-  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_compress<TF64>), device)
-                    : max_grid_of(reinterpret_cast<const void*>(&k_compress<TF32>), device);
+  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_compress<TF64>), device, 64 * kWavesC)
+                    : max_grid_of(reinterpret_cast<const void*>(&k_compress<TF32>), device, 64 * kWavesC);
 }
 int max_grid_decompress(int device, int dtype) {
-  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF64>), device)
-                    : max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF32>), device);
+  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF64>), device, 64 * kWavesD)
+                    : max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF32>), device, 64 * kWavesD);
 }
 
 }  // namespace falcon_dev
