@@ -87,6 +87,39 @@ def cpu_baseline(x, budget_s=12.0):
     }
 
 
+def host_pipeline(codec, x, torch, reps=2):
+    """Host -> host through the stream pipeline (Alg. 1), from pinned and
+    from pageable host buffers; best of reps, GB/s of original bytes."""
+    res = {"n_streams": 16, "batch_chunks": 4096}
+    codec.set_pipeline(16, 4096)
+    for kind in ("pinned", "pageable"):
+        xh = torch.from_numpy(x)
+        if kind == "pinned":
+            xh = xh.pin_memory()
+        cap = codec_bound(x)
+        sbuf = torch.empty(cap, dtype=torch.uint8, pin_memory=(kind == "pinned"))
+        ybuf = torch.empty(x.size, dtype=xh.dtype, pin_memory=(kind == "pinned"))
+        tc = td = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            s = codec.compress_host(xh, out=sbuf)
+            t1 = time.perf_counter()
+            y = codec.decompress_host(s, out=ybuf)
+            t2 = time.perf_counter()
+            tc, td = min(tc, t1 - t0), min(td, t2 - t1)
+        assert torch.equal(y.view(torch.uint8), xh.view(torch.uint8)), "host round trip failed"
+        res[kind] = {"compress_gbps": round(x.nbytes / tc / 1e9, 3),
+                     "decompress_gbps": round(x.nbytes / td / 1e9, 3)}
+        del xh, sbuf, ybuf, s, y
+    return res
+
+
+def codec_bound(x):
+    from paper_2511_04140_amd import codec as C
+    import torch
+    return C.compress_bound(x.size, torch.float64 if x.dtype.itemsize == 8 else torch.float32)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 28, help="values (default: the 2 GiB workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host", action="store_true", help="skip the host -> host pipeline measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of the input "
                          "(2 GiB read + 2 GiB write) as the reference for HBM byte counters")
@@ -193,6 +227,9 @@ def main():
                               (min(kc_ms, kd_ms) * 1e-3) / 1e9, 2),
         },
     }
+    if not args.no_host:
+        del sbuf, ybuf, s, y
+        out["host_pipeline"] = host_pipeline(codec, x, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x)
     codec.close()

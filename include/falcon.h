@@ -94,6 +94,40 @@ falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falco
 falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len, void* d_out,
                                 size_t out_cap_bytes, size_t* n_out, void* stream);
 
+/* Host -> host compression through the asynchronous pipeline of Sec. 3.1
+ * (Alg. 1, event-driven scheduler).  The n values at h_in (host) are cut
+ * into batches of whole chunks; each of the context's pipeline streams
+ * copies a batch to the device, compresses it, reads back its payload byte
+ * count, and -- once every batch launched before it has been placed --
+ * copies its chunk sizes and payload to their final place in h_out (host,
+ * out_cap bytes).  The result is byte-identical to falcon_compress of the
+ * same values.  Pinned (hipHostMalloc) buffers are transferred directly;
+ * pageable ones are staged through pinned buffers the context owns.
+ * Synchronous: returns when h_out is complete.  If out_cap is below
+ * falcon_compress_bound(n, dt), returns FALCON_ERR_BUFFER_TOO_SMALL and
+ * sets *out_len to that bound. */
+falcon_status falcon_compress_host(falcon_ctx* ctx, const void* h_in, size_t n, falcon_dtype dt, void* h_out,
+                                   size_t out_cap, size_t* out_len);
+
+/* Host -> host decompression of the stream of in_len bytes at h_in (host)
+ * into h_out (host, out_cap_bytes bytes).  Sec. 4: the chunk sizes are in
+ * host memory, so every batch's payload offset is known before any
+ * transfer (pre-allocation); the pipeline streams each copy a batch's sizes
+ * and payload to the device, decode it and copy the values to their place.
+ * The size array is checked on the host, every chunk on the device; errors
+ * as for falcon_decompress. */
+falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t in_len, void* h_out,
+                                     size_t out_cap_bytes, size_t* n_out);
+
+/* Sets the pipeline geometry used by the two calls above: n_streams HIP
+ * streams (1..64; N_s of Alg. 1) and batch_chunks chunks of 1025 values per
+ * batch (1..2^20).  Defaults: 16 streams, 4096 chunks (Sec. 5.1.4 setting).
+ * Device and pinned buffers (about 2 x 33.6 MB per stream at the default
+ * batch, twice that when pageable buffers are staged) are allocated on
+ * first use and kept until the geometry changes or the context is
+ * destroyed.  FALCON_ERR_INVALID_ARG outside the ranges. */
+falcon_status falcon_set_pipeline(falcon_ctx* ctx, int n_streams, size_t batch_chunks);
+
 /* Parses a stream header held in host memory (len >= 32 bytes) and returns
  * the value count and dtype.  FALCON_ERR_CORRUPT_STREAM if the header is not
  * a version-1 Falcon header. */

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfalcon.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.cpp", "pipeline.cpp")]
 ARCH = os.environ.get("FALCON_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -25,7 +25,10 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1], "-o", tmp]
+    cmd = [hipcc, *FLAGS]
+    for src in SOURCES:
+        cmd += ["-x", "hip", src]
+    cmd += ["-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

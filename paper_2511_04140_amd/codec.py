@@ -50,6 +50,12 @@ def _load():
     L.falcon_stream_info.restype = i
     L.falcon_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.falcon_last_kernel_ms.restype = i
+    L.falcon_compress_host.argtypes = [vp, vp, sz, i, vp, sz, ctypes.POINTER(sz)]
+    L.falcon_compress_host.restype = i
+    L.falcon_decompress_host.argtypes = [vp, vp, sz, vp, sz, ctypes.POINTER(sz)]
+    L.falcon_decompress_host.restype = i
+    L.falcon_set_pipeline.argtypes = [vp, i, sz]
+    L.falcon_set_pipeline.restype = i
     L.falcon_status_str.argtypes = [i]
     L.falcon_status_str.restype = ctypes.c_char_p
     return L
@@ -153,6 +159,53 @@ class Codec:
                                      _stream_handle(stream.device))
         if st != 0:
             raise FalconError(st, "falcon_decompress")
+        return out[: nout.value]
+
+    # -- host -> host through the stream pipeline ---------------------------
+    def set_pipeline(self, n_streams: int = 16, batch_chunks: int = 4096):
+        """Pipeline geometry: N_s streams, batch_chunks chunks per batch."""
+        st = lib().falcon_set_pipeline(self._ctx, n_streams, batch_chunks)
+        if st != 0:
+            raise FalconError(st, "falcon_set_pipeline")
+
+    def compress_host(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Compresses a contiguous float32/float64 host tensor through the
+        pipeline; returns the stream as a uint8 host tensor (a view of `out`
+        when given; pinned when x is pinned)."""
+        if x.is_cuda or not x.is_contiguous():
+            raise ValueError("compress_host needs a contiguous host tensor")
+        code = _dtype_code(x.dtype)
+        n = x.numel()
+        cap = lib().falcon_compress_bound(n, code)
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, pin_memory=x.is_pinned())
+        olen = ctypes.c_size_t()
+        st = lib().falcon_compress_host(self._ctx, ctypes.c_void_p(x.data_ptr() if n else 0), n, code,
+                                        ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(olen))
+        if st != 0:
+            raise FalconError(st, "falcon_compress_host")
+        return out[: olen.value]
+
+    def decompress_host(self, stream: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Decompresses a uint8 host tensor holding one stream through the
+        pipeline; returns a host tensor of the stream's dtype."""
+        if stream.is_cuda or stream.dtype != torch.uint8 or not stream.is_contiguous():
+            raise ValueError("decompress_host needs a contiguous uint8 host tensor")
+        n = ctypes.c_size_t()
+        code = ctypes.c_int()
+        st = lib().falcon_stream_info(ctypes.c_void_p(stream.data_ptr()), stream.numel(), ctypes.byref(n),
+                                      ctypes.byref(code))
+        if st != 0:
+            raise FalconError(st, "falcon_stream_info")
+        dt = torch.float64 if code.value == FALCON_FLOAT64 else torch.float32
+        if out is None:
+            out = torch.empty(n.value, dtype=dt, pin_memory=stream.is_pinned())
+        nout = ctypes.c_size_t()
+        st = lib().falcon_decompress_host(self._ctx, ctypes.c_void_p(stream.data_ptr()), stream.numel(),
+                                          ctypes.c_void_p(out.data_ptr() if out.numel() else 0),
+                                          out.numel() * out.element_size(), ctypes.byref(nout))
+        if st != 0:
+            raise FalconError(st, "falcon_decompress_host")
         return out[: nout.value]
 
 

@@ -1,0 +1,99 @@
+// context.hpp -- host-side state of a Falcon context, shared by the C ABI
+// translation units (api.cpp, pipeline.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/falcon.h"
+#include "internal.hpp"
+
+namespace falcon_host {
+
+constexpr uint64_t kChunkN = 1025;
+constexpr size_t kF64Chunk = 8211, kF32Chunk = 4107;  // largest chunk payloads
+constexpr size_t kStageBytes = 64;                    // pinned bytes per lane
+
+inline size_t elem_size(falcon_dtype dt) { return dt == FALCON_FLOAT64 ? 8 : dt == FALCON_FLOAT32 ? 4 : 0; }
+inline size_t max_chunk_bytes(falcon_dtype dt) {
+  return dt == FALCON_FLOAT64 ? kF64Chunk : dt == FALCON_FLOAT32 ? kF32Chunk : 0;
+}
+inline uint64_t chunks_of(uint64_t n) { return (n + kChunkN - 1) / kChunkN; }
+inline uint64_t groups_of(uint64_t nchunks) { return (nchunks + 63) / 64; }
+inline uint32_t rd32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
+inline uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
+inline falcon_status dev_err(hipError_t e) { return e == hipSuccess ? FALCON_OK : FALCON_ERR_DEVICE; }
+
+// Writes the 32-byte stream header (format in falcon.h) to host memory.
+void write_header(uint8_t* h, falcon_dtype dt, uint64_t n, uint64_t payload);
+
+// One independent launch queue: a stream and the device scratch that a
+// compression or decompression launch needs for itself (look-back status
+// words, control block).  Launches on different lanes may run concurrently.
+struct Lane {
+  hipStream_t stream = nullptr;
+  uint64_t* status = nullptr;   // one word per chunk (compress: look-back; decompress: offsets)
+  size_t status_cap = 0;
+  uint64_t* gstatus = nullptr;  // one word per 64-chunk group, plus scan tile sums
+  size_t gstatus_cap = 0;
+  falcon_dev::Ctl* ctl = nullptr;
+  uint8_t* stage = nullptr;     // pinned host bytes: [0,32) header, [32,36) error word, [40,48) payload size
+  uint32_t epoch = 0;
+};
+
+falcon_status lane_init(Lane& l);
+void lane_free(Lane& l);
+
+// State of one stream of the host <-> device pipeline (Alg. 1).
+struct PipeLane {
+  Lane lane;
+  uint8_t* g_in = nullptr;   // device batch buffers
+  uint8_t* g_out = nullptr;
+  uint8_t* p_in = nullptr;   // pinned host staging, used for pageable caller buffers
+  uint8_t* p_out = nullptr;
+  hipEvent_t ev = nullptr;
+  int state = 0;
+  uint64_t c0 = 0, nchunks = 0, nvals = 0, cs = 0, dst = 0;
+};
+
+}  // namespace falcon_host
+
+struct falcon_ctx {
+  int device = 0;
+  falcon_host::Lane main;
+  int grid_c[3] = {0, 0, 0};  // co-resident workgroups per kernel, by dtype
+  int grid_d[3] = {0, 0, 0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last timed kernel
+  bool timed = false;
+  // host <-> device pipeline
+  int pipe_streams = 16;
+  uint64_t pipe_batch_chunks = 4096;
+  size_t pipe_buf_bytes = 0;     // bytes of each g_in / g_out / p_in / p_out
+  bool pipe_staging = false;     // p_in / p_out allocated
+  std::vector<falcon_host::PipeLane> pipe;
+};
+
+namespace falcon_host {
+
+// Enqueues the compression of n values at d_in into the stream buffer d_out
+// on lane l (stream s).  Nothing is waited for; the stream's payload byte
+// count lands in the stream header at d_out + 24.  With timed, events
+// around the kernel feed falcon_last_kernel_ms.
+falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
+                               hipStream_t s, bool timed);
+
+// Enqueues the decompression of a stream at d_in whose header (n, dt,
+// payload) the host already knows and has checked, into d_out, followed by
+// a copy of the error word into l.stage + 32.  decompress_failed() afterwards
+// (once the stream has reached that copy) tells whether a chunk failed.
+falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t n, falcon_dtype dt,
+                                 uint64_t payload, void* d_out, hipStream_t s, bool timed);
+inline bool decompress_failed(const Lane& l) { return rd32(l.stage + 32) == l.epoch; }
+
+// Frees the pipeline lanes and their buffers (pipeline.cpp).
+void pipe_release(falcon_ctx* ctx);
+
+}  // namespace falcon_host
