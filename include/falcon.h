@@ -128,6 +128,76 @@ falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t i
  * destroyed.  FALCON_ERR_INVALID_ARG outside the ranges. */
 falcon_status falcon_set_pipeline(falcon_ctx* ctx, int n_streams, size_t batch_chunks);
 
+/* ---- Many series in one launch ----------------------------------------
+ * One series of a batch call or plan.  Compression: d_in holds n values of
+ * type dtype (device), d_out (device, out_cap bytes, 4-byte aligned) receives
+ * the stream, out_len its length.  Decompression: d_in holds a stream of
+ * in_len bytes (device, 4-byte aligned) that must hold n values of type
+ * dtype (the count and dtype the caller compressed, or falcon_stream_info of
+ * its header); d_out (device, out_cap bytes) receives the values, out_len = n.
+ * Each series' output is byte-identical to a one-series call on it. */
+typedef struct falcon_series {
+  const void* d_in;
+  size_t n;
+  size_t in_len;
+  void* d_out;
+  size_t out_cap;
+  falcon_dtype dtype;
+  size_t out_len;
+} falcon_series;
+
+typedef enum { FALCON_OP_COMPRESS = 0, FALCON_OP_DECOMPRESS = 1 } falcon_op;
+
+/* Plan flags: FALCON_PLAN_TUNE times every launch geometry candidate on the
+ * plan's own series and keeps the fastest; FALCON_PLAN_GRAPH records the
+ * plan's launches as one HIP graph replayed by falcon_plan_run. */
+enum { FALCON_PLAN_TUNE = 1, FALCON_PLAN_GRAPH = 2 };
+
+typedef struct falcon_plan falcon_plan;
+
+typedef struct falcon_plan_info {
+  int split;            /* 1: one launch per dtype; 0: one launch over both dtypes */
+  int waves_per_group;  /* wavefronts per workgroup */
+  int grid_percent;     /* grid as a percentage of the co-resident workgroups */
+  int candidates;       /* geometries timed by the autotuner (0: not tuned) */
+  float best_ms;        /* autotuner: time of the chosen geometry */
+  float default_ms;     /* autotuner: time of the default geometry */
+  int graph;            /* 1 if runs replay a HIP graph */
+  uint64_t total_chunks;
+} falcon_plan_info;
+
+/* Compresses count series in one launch sequence (no tuning, no graph):
+ * every chunk of every series is a work item of the same persistent
+ * kernel, whose decoupled look-back (Sec. 3.4) runs per series.  Sets each
+ * s[i].out_len.  Series are checked on the host first: a bad descriptor
+ * returns FALCON_ERR_INVALID_ARG / FALCON_ERR_BUFFER_TOO_SMALL before any
+ * launch.  Synchronous. */
+falcon_status falcon_compress_batch(falcon_ctx* ctx, falcon_series* s, size_t count, void* stream);
+
+/* Decompresses count streams in one launch sequence (Sec. 4 per series):
+ * headers checked on the device against the descriptors, one scan over the
+ * sizes of all series, one decoding launch.  Errors as falcon_decompress;
+ * FALCON_ERR_CORRUPT_STREAM if any series fails. */
+falcon_status falcon_decompress_batch(falcon_ctx* ctx, falcon_series* s, size_t count, void* stream);
+
+/* Builds a reusable plan for op over count series (1 <= count < 2^31).  The
+ * plan keeps the series' device pointers, sizes and dtypes; the contents of
+ * the buffers may change between runs.  It owns its scratch, so plans run
+ * independently of each other and of one-series calls on the context.
+ * flags: FALCON_PLAN_TUNE, FALCON_PLAN_GRAPH (above).  Tuning runs the
+ * operation on the series several times (outputs are written). */
+falcon_status falcon_plan_create(falcon_ctx* ctx, falcon_op op, const falcon_series* s, size_t count,
+                                 unsigned flags, falcon_plan** out);
+
+/* Runs a plan on `stream` (NULL: the plan's own) and waits for it; fills
+ * s[i].out_len if s is not NULL (s must then have the plan's count). */
+falcon_status falcon_plan_run(falcon_plan* p, falcon_series* s, void* stream);
+
+/* Reports the plan's launch geometry and tuning record. */
+falcon_status falcon_plan_describe(const falcon_plan* p, falcon_plan_info* info);
+
+void falcon_plan_destroy(falcon_plan* p);
+
 /* Parses a stream header held in host memory (len >= 32 bytes) and returns
  * the value count and dtype.  FALCON_ERR_CORRUPT_STREAM if the header is not
  * a version-1 Falcon header. */

@@ -29,6 +29,26 @@ class FalconError(RuntimeError):
         self.status = status
 
 
+class Series(ctypes.Structure):
+    """falcon_series of falcon.h."""
+    _fields_ = [("d_in", ctypes.c_void_p), ("n", ctypes.c_size_t), ("in_len", ctypes.c_size_t),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_size_t), ("dtype", ctypes.c_int),
+                ("out_len", ctypes.c_size_t)]
+
+
+class PlanInfo(ctypes.Structure):
+    """falcon_plan_info of falcon.h."""
+    _fields_ = [("split", ctypes.c_int), ("waves_per_group", ctypes.c_int), ("grid_percent", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("graph", ctypes.c_int), ("total_chunks", ctypes.c_uint64)]
+
+
+OP_COMPRESS = 0
+OP_DECOMPRESS = 1
+PLAN_TUNE = 1
+PLAN_GRAPH = 2
+
+
 def _load():
     if not os.path.exists(lib_path):
         raise ImportError(
@@ -56,6 +76,19 @@ def _load():
     L.falcon_decompress_host.restype = i
     L.falcon_set_pipeline.argtypes = [vp, i, sz]
     L.falcon_set_pipeline.restype = i
+    ps = ctypes.POINTER(Series)
+    L.falcon_compress_batch.argtypes = [vp, ps, sz, vp]
+    L.falcon_compress_batch.restype = i
+    L.falcon_decompress_batch.argtypes = [vp, ps, sz, vp]
+    L.falcon_decompress_batch.restype = i
+    L.falcon_plan_create.argtypes = [vp, i, ps, sz, ctypes.c_uint, ctypes.POINTER(vp)]
+    L.falcon_plan_create.restype = i
+    L.falcon_plan_run.argtypes = [vp, ps, vp]
+    L.falcon_plan_run.restype = i
+    L.falcon_plan_describe.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.falcon_plan_describe.restype = i
+    L.falcon_plan_destroy.argtypes = [vp]
+    L.falcon_plan_destroy.restype = None
     L.falcon_status_str.argtypes = [i]
     L.falcon_status_str.restype = ctypes.c_char_p
     return L
@@ -207,6 +240,100 @@ class Codec:
         if st != 0:
             raise FalconError(st, "falcon_decompress_host")
         return out[: nout.value]
+
+    # -- many series in one launch ------------------------------------------
+    def _compress_descs(self, xs, outs):
+        descs = (Series * len(xs))()
+        views = []
+        for i, x in enumerate(xs):
+            if not x.is_cuda or not x.is_contiguous():
+                raise ValueError("batch compression needs contiguous device tensors")
+            code = _dtype_code(x.dtype)
+            cap = lib().falcon_compress_bound(x.numel(), code)
+            o = outs[i] if outs is not None else torch.empty(cap, dtype=torch.uint8, device=x.device)
+            descs[i] = Series(x.data_ptr() if x.numel() else None, x.numel(), 0, o.data_ptr(), o.numel(), code, 0)
+            views.append(o)
+        return descs, views
+
+    def _decompress_descs(self, streams, counts, dtypes, outs):
+        descs = (Series * len(streams))()
+        views = []
+        for i, s_ in enumerate(streams):
+            if not s_.is_cuda or s_.dtype != torch.uint8 or not s_.is_contiguous():
+                raise ValueError("batch decompression needs contiguous uint8 device tensors")
+            code = _dtype_code(dtypes[i])
+            o = outs[i] if outs is not None else torch.empty(counts[i], dtype=dtypes[i], device=s_.device)
+            descs[i] = Series(s_.data_ptr(), counts[i], s_.numel(), o.data_ptr() if o.numel() else None,
+                              o.numel() * o.element_size(), code, 0)
+            views.append(o)
+        return descs, views
+
+    def compress_batch(self, xs, outs=None):
+        """Compresses a list of float32/float64 device tensors in one launch
+        sequence; returns the streams (views of `outs` when given)."""
+        descs, views = self._compress_descs(xs, outs)
+        st = lib().falcon_compress_batch(self._ctx, descs, len(xs), _stream_handle(self.device))
+        if st != 0:
+            raise FalconError(st, "falcon_compress_batch")
+        return [v[: descs[i].out_len] for i, v in enumerate(views)]
+
+    def decompress_batch(self, streams, counts, dtypes, outs=None):
+        """Decompresses a list of streams (uint8 device tensors) holding
+        counts[i] values of dtypes[i] each, in one launch sequence."""
+        descs, views = self._decompress_descs(streams, counts, dtypes, outs)
+        st = lib().falcon_decompress_batch(self._ctx, descs, len(streams), _stream_handle(self.device))
+        if st != 0:
+            raise FalconError(st, "falcon_decompress_batch")
+        return views
+
+    def plan_compress(self, xs, outs=None, tune=True, graph=True):
+        descs, views = self._compress_descs(xs, outs)
+        return Plan(self, OP_COMPRESS, descs, views, tune, graph)
+
+    def plan_decompress(self, streams, counts, dtypes, outs=None, tune=True, graph=True):
+        descs, views = self._decompress_descs(streams, counts, dtypes, outs)
+        return Plan(self, OP_DECOMPRESS, descs, views, tune, graph)
+
+
+class Plan:
+    """A reusable batch launch (falcon_plan): fixed series buffers, tuned
+    geometry, optionally replayed as a HIP graph."""
+
+    def __init__(self, codec: Codec, op: int, descs, views, tune: bool, graph: bool):
+        self.codec, self.op, self.descs, self.views = codec, op, descs, views
+        self._p = ctypes.c_void_p()
+        flags = (PLAN_TUNE if tune else 0) | (PLAN_GRAPH if graph else 0)
+        st = lib().falcon_plan_create(codec._ctx, op, descs, len(descs), flags, ctypes.byref(self._p))
+        if st != 0:
+            raise FalconError(st, "falcon_plan_create")
+
+    def run(self, stream=None):
+        """Runs the plan; returns the outputs (streams trimmed to length)."""
+        h = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        st = lib().falcon_plan_run(self._p, self.descs, h)
+        if st != 0:
+            raise FalconError(st, "falcon_plan_run")
+        if self.op == OP_COMPRESS:
+            return [v[: self.descs[i].out_len] for i, v in enumerate(self.views)]
+        return self.views
+
+    def info(self) -> dict:
+        pi = PlanInfo()
+        st = lib().falcon_plan_describe(self._p, ctypes.byref(pi))
+        if st != 0:
+            raise FalconError(st, "falcon_plan_describe")
+        return {f: getattr(pi, f) for f, _ in PlanInfo._fields_}
+
+    def close(self):
+        if self._p:
+            lib().falcon_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default: dict = {}

@@ -110,14 +110,15 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.status = l.status;
   a.gstatus = l.gstatus;
   a.ctl = l.ctl;
+  a.lens = nullptr;
   a.epoch = l.epoch;
-  const int grid = grid_for(ctx->grid_c[dt], nc, kCompressWaves);
+  const int grid = grid_for(max_grid_c(ctx, dt, kCompressWaves), nc, kCompressWaves);
   a.total_waves = (uint32_t)(grid * kCompressWaves);
   if (timed) {
     ctx->timed = false;
     if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   }
-  if ((st = dev_err(launch_compress(a, (int)dt, grid, s))) != FALCON_OK) return st;
+  if ((st = dev_err(launch_compress(a, (int)dt, kCompressWaves, grid, s))) != FALCON_OK) return st;
   if (timed) {
     if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
     ctx->timed = true;
@@ -153,7 +154,8 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   a.status = l.status;
   a.ctl = l.ctl;
   a.epoch = l.epoch;
-  const int grid = grid_for(ctx->grid_d[dt], nc, kDecompressWaves);
+  a.relative = 0;
+  const int grid = grid_for(max_grid_d(ctx, dt), nc, kDecompressWaves);
   a.total_waves = (uint32_t)(grid * kDecompressWaves);
   if (timed && (st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   if ((st = dev_err(launch_decompress(a, (int)dt, grid, s))) != FALCON_OK) return st;
@@ -202,9 +204,10 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
-  for (int dt = 1; dt <= 2; ++dt) {
-    ctx->grid_c[dt] = max_grid_compress(device, dt);
-    ctx->grid_d[dt] = max_grid_decompress(device, dt);
+  for (int form = 1; form <= 3; ++form) {
+    ctx->grid_c[form][0] = max_grid_compress(device, form, 8);
+    ctx->grid_c[form][1] = max_grid_compress(device, form, 16);
+    ctx->grid_d[form] = max_grid_decompress(device, form);
   }
   *out = ctx;
   return FALCON_OK;

@@ -1,4 +1,5 @@
-// kernels.hip -- Falcon compression and decompression kernels for gfx950.
+// codec_kernels.hpp -- Falcon compression and decompression kernels for
+// gfx950 (device code; each kernels_*.hip instantiates one form).
 //
 // Both kernels are persistent: each wavefront repeatedly takes a ticket (the
 // next chunk in stream order) from a device counter, processes the chunk,
@@ -6,6 +7,8 @@
 // the order in which waves start, which the decoupled look-back needs for
 // forward progress (a chunk only waits for chunks whose owners are already
 // running).
+#pragma once
+
 #include <type_traits>
 
 #include "codec_device.hpp"
@@ -365,7 +368,7 @@ __device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf
 template <class T>
 __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries& sd, uint64_t c, uint64_t nc,
                                               uint64_t t, uint64_t* status, uint64_t* gstatus, uint32_t epoch,
-                                              int lane_in, const ChunkPlanes& cp) {
+                                              uint64_t* lens, int lane_in, const ChunkPlanes& cp) {
   int lane = lane_in;  // opaque, see compress_front
   asm volatile("" : "+v"(lane));
   const uint32_t w = cp.w;
@@ -465,7 +468,10 @@ __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries
     }
   }
   if (lane == 0) reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = S;
-  if (c == nc - 1) write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
+  if (c == nc - 1) {
+    write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
+    if (lens && lane == 0) lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
+  }
   wave_lds_sync();
 }
 
@@ -475,7 +481,7 @@ __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries
 template <class T>
 __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* buf, const DecompressSeries& sd,
                                                  uint64_t c, uint64_t nc, uint64_t t, const uint64_t* offsets,
-                                                 uint32_t epoch, int lane_in, Ctl* ctl) {
+                                                 uint64_t off_base, uint32_t epoch, int lane_in, Ctl* ctl) {
   using U = typename T::U;
   using F = typename T::F;
   using S_ = typename T::S;
@@ -483,11 +489,14 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   asm volatile("" : "+v"(lane));
   const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
   const uint32_t S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
-  // d1: chunk offset, from the prefix scan of the size array (k_scan_*),
-  // which also checked every size against [3 + ZB, BOUND] and their sum
-  // against the payload byte count.
-  const uint64_t off = uniform64(offsets[t]);
-  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB) || off + S > sd.payload_bytes;
+  // d1: chunk offset, from the prefix scan of the size array (k_scan_*).
+  // In a batch launch the scan runs over the sizes of all series and a
+  // series subtracts the offset of its first chunk (off_base).  Every size
+  // must lie in [3 + ZB, BOUND] and the series' sizes must add up to its
+  // payload byte count (checked by its last chunk).
+  const uint64_t off = uniform64(offsets[t]) - off_base;
+  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB) || off + S > sd.payload_bytes ||
+             (c == nc - 1 && off + S != sd.payload_bytes);
   if (bad) {
     if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -634,7 +643,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
 // ---------------------------------------------------------------------------
 template <class Series>
 __device__ __forceinline__ Series find_series(const Series& one, const Series* many, uint32_t ns, uint64_t t) {
-  if (ns <= 1) return one;
+  if (!many) return one;  // one-series launch: the descriptor travels in the arguments
   uint32_t lo = 0, hi = ns - 1;  // last series with chunk0 <= t
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
@@ -703,18 +712,56 @@ __device__ __forceinline__ uint64_t resolve_slot(BlockLdsT<NW>& sm, TicketClaim 
   return (uint64_t)b * NW + tc.pos;
 }
 
+// Writes the 32-byte header of every empty series of a batch launch and its
+// stream length (no chunk of the launch belongs to them).  Run by the first
+// workgroup of a batch launch (one with a length array), one thread per
+// series.
+__device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
+  if (!a.lens || blockIdx.x != 0) return;
+  for (uint32_t i = threadIdx.x; i < a.nseries; i += blockDim.x) {
+    const CompressSeries& sd = a.many[i];
+    if (sd.n != 0) continue;
+    uint32_t* o = reinterpret_cast<uint32_t*>(sd.out);
+    o[0] = 0x4E434C46u;  // "FLCN"
+    o[1] = 1u | (sd.dtype << 8);
+    o[2] = (uint32_t)kChunk;
+    o[3] = o[4] = o[5] = o[6] = o[7] = 0;
+    if (a.lens) a.lens[sd.idx] = kHdrBytes;
+  }
+}
+
+// One chunk of compression, a1-a11, by one wave.
 template <class T>
-__global__ __launch_bounds__(64 * kWavesC) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
-  __shared__ BlockLdsT<kWavesC> sm;
+__device__ __forceinline__ void compress_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
+                                               const CompressSeries& sd, uint64_t t, int lane,
+                                               typename T::U (&vb)[17]) {
+  const uint64_t c = t - sd.chunk0;
+  load_chunk<T>(sd, c, lane, vb);
+  ChunkPlanes cp;
+  compress_front<T>(tab, buf, vb, lane, cp);
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  compress_back<T>(buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, a.lens, lane, cp);
+}
+
+template <int NW>
+__device__ __forceinline__ void compress_prologue(BlockLdsT<NW>& sm, const CompressArgs& a) {
   load_tables(sm.tab);
   if (threadIdx.x == 0) sm.slot_next = 0;
   if (threadIdx.x < 8) sm.ring_round[threadIdx.x] = 0xFFFFFFFFu;
+  empty_series_headers(a);
   __syncthreads();
+}
+
+// One dtype per launch.  A chunk is claimed only when the wave is ready to
+// work on it: a claimed chunk that waited behind another chunk's look-back
+// would delay its own size, and with it the look-back of every chunk after
+// it.
+template <class T, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  compress_prologue(sm, a);
   const int lane = lane_id();
   uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  // A chunk is claimed only when the wave is ready to work on it: a claimed
-  // chunk that waited behind another chunk's look-back would delay its own
-  // size, and with it the look-back of every chunk after it.
   typename T::U vb[17];
   for (;;) {
     const uint64_t t = resolve_slot(sm, claim_slot(sm, a.ctl, lane), lane);
@@ -722,19 +769,47 @@ __global__ __launch_bounds__(64 * kWavesC) __attribute__((amdgpu_waves_per_eu(4)
       if (t == 0 && a.nseries == 1) write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
       break;
     }
-    const CompressSeries sd = find_series(a.one, a.many, a.nseries, t);
-    const uint64_t c = t - sd.chunk0;
-    load_chunk<T>(sd, c, lane, vb);
-    ChunkPlanes cp;
-    compress_front<T>(sm.tab, buf, vb, lane, cp);
-    const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    compress_back<T>(buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, lane, cp);
+    const uint64_t tg = t + a.t0;
+    compress_chunk<T>(sm.tab, buf, a, find_series(a.one, a.many, a.nseries, tg), tg, lane, vb);
+  }
+  exit_protocol(a.ctl, a.total_waves, lane);
+}
+
+// Series of both dtypes in one launch: the wave branches on the dtype of
+// the chunk's series (uniform across the wave).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_mixed(CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  compress_prologue(sm, a);
+  const int lane = lane_id();
+  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
+  for (;;) {
+    const uint64_t t = resolve_slot(sm, claim_slot(sm, a.ctl, lane), lane);
+    if (t >= a.total_chunks) break;
+    const uint64_t tg = t + a.t0;
+    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    if (uniform(sd.dtype) == 2) {
+      uint64_t vb[17];
+      compress_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
+    } else {
+      uint32_t vb[17];
+      compress_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
+    }
   }
   exit_protocol(a.ctl, a.total_waves, lane);
 }
 
 // Decompression has no dependence between chunks once the offsets are
 // known, so waves take chunks by static striding and use no counter.
+template <class T>
+__device__ __forceinline__ void decompress_one(const LdsTables& tab, uint8_t* buf, const DecompressArgs& a,
+                                               const DecompressSeries& sd, uint64_t t, int lane) {
+  const uint64_t c = t - sd.chunk0;
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  const uint64_t base = a.relative ? uniform64(a.status[sd.chunk0]) : 0;
+  decompress_chunk<T>(tab, buf, sd, c, nc, t, a.status, base, a.epoch, lane, a.ctl);
+}
+
 template <class T>
 __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
   __shared__ BlockLdsT<kWavesD> sm;
@@ -744,137 +819,9 @@ __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4)
   uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
   const uint64_t w0 = (uint64_t)blockIdx.x * kWavesD + (threadIdx.x >> 6);
   for (uint64_t t = w0; t < a.total_chunks; t += a.total_waves) {
-    const DecompressSeries sd = find_series(a.one, a.many, a.nseries, t);
-    const uint64_t c = t - sd.chunk0;
-    const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-    decompress_chunk<T>(sm.tab, buf, sd, c, nc, t, a.status, a.epoch, lane, a.ctl);
+    const uint64_t tg = t + a.t0;
+    decompress_one<T>(sm.tab, buf, a, find_series(a.one, a.many, a.nseries, tg), tg, lane);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Prefix sum of a chunk size array into chunk offsets (decompression, Sec. 4:
-// the size array is scanned into the offset array).  Three small kernels over
-// tiles of kScanTile sizes: tile sums, a scan of the tile sums (which also
-// checks the total against the payload byte count), and the per-tile scan.
-// Sizes outside [lo, hi] set the error word.
-// ---------------------------------------------------------------------------
-constexpr int kScanTile = 4096;  // 256 threads x 16 sizes
-
-__device__ __forceinline__ uint64_t block_excl_scan256(uint64_t v, uint64_t* tmp, uint64_t& total) {
-  // tmp: 4 words of LDS (one per wave)
-  const int lane = lane_id(), wid = threadIdx.x >> 6;
-  const uint64_t incl = wave_incl_scan64(v, lane);
-  if (lane == 63) tmp[wid] = incl;
-  __syncthreads();
-  uint64_t before = 0;
-  for (int i = 0; i < wid; ++i) before += tmp[i];
-  total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
-  __syncthreads();
-  return before + incl - v;
-}
-
-__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi,
-                                                    uint64_t* tile_sum, Ctl* ctl, uint32_t epoch) {
-  __shared__ uint64_t tmp[4];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * 16;
-  uint64_t sum = 0;
-  bool bad = false;
-  for (int k = 0; k < 16; ++k) {
-    if (base + k < n) {
-      const uint32_t v = sizes[base + k];
-      bad |= v < lo || v > hi;
-      sum += v;
-    }
-  }
-  if (bad) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t total;
-  block_excl_scan256(sum, tmp, total);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_tile_sums(uint64_t* tile_sum, uint64_t ntiles, uint64_t expect,
-                                                        Ctl* ctl, uint32_t epoch) {
-  __shared__ uint64_t tmp[4];
-  uint64_t carry = 0;
-  for (uint64_t b0 = 0; b0 < ntiles; b0 += 256) {
-    const uint64_t i = b0 + threadIdx.x;
-    const uint64_t v = i < ntiles ? tile_sum[i] : 0;
-    uint64_t total;
-    const uint64_t ex = block_excl_scan256(v, tmp, total);
-    if (i < ntiles) tile_sum[i] = carry + ex;  // becomes the tile's offset
-    carry += total;
-  }
-  if (threadIdx.x == 0 && carry != expect)
-    __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* sizes, uint64_t n, const uint64_t* tile_off,
-                                                    uint64_t* offsets) {
-  __shared__ uint64_t tmp[4];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * 16;
-  uint32_t v[16];
-  uint64_t sum = 0;
-  for (int k = 0; k < 16; ++k) {
-    v[k] = base + k < n ? sizes[base + k] : 0u;
-    sum += v[k];
-  }
-  uint64_t total;
-  uint64_t run = tile_off[blockIdx.x] + block_excl_scan256(sum, tmp, total);
-  for (int k = 0; k < 16; ++k) {
-    if (base + k < n) offsets[base + k] = run;
-    run += v[k];
-  }
-}
-
-__global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s) {
-  if (dtype == 2) hipLaunchKernelGGL(k_compress<TF64>, dim3(grid), dim3(64 * kWavesC), 0, s, a);
-  else hipLaunchKernelGGL(k_compress<TF32>, dim3(grid), dim3(64 * kWavesC), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s) {
-  if (dtype == 2) hipLaunchKernelGGL(k_decompress<TF64>, dim3(grid), dim3(64 * kWavesD), 0, s, a);
-  else hipLaunchKernelGGL(k_decompress<TF32>, dim3(grid), dim3(64 * kWavesD), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_scan_sizes(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi, uint64_t expect,
-                             uint64_t* tile_tmp, uint64_t* offsets, Ctl* ctl, uint32_t epoch, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, sizes, n, lo, hi, tile_tmp, ctl, epoch);
-  hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(256), 0, s, tile_tmp, ntiles, expect, ctl, epoch);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, s, sizes, n, tile_tmp, offsets);
-  return hipGetLastError();
-}
-uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
-
-hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-static int max_grid_of(const void* fn, int device, int block) {
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  return per_cu * prop.multiProcessorCount;
-}
-int max_grid_compress(int device, int dtype) {
-  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_compress<TF64>), device, 64 * kWavesC)
-                    : max_grid_of(reinterpret_cast<const void*>(&k_compress<TF32>), device, 64 * kWavesC);
-}
-int max_grid_decompress(int device, int dtype) {
-  return dtype == 2 ? max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF64>), device, 64 * kWavesD)
-                    : max_grid_of(reinterpret_cast<const void*>(&k_decompress<TF32>), device, 64 * kWavesD);
 }
 
 }  // namespace falcon_dev

@@ -64,8 +64,10 @@ struct PipeLane {
 struct falcon_ctx {
   int device = 0;
   falcon_host::Lane main;
-  int grid_c[3] = {0, 0, 0};  // co-resident workgroups per kernel, by dtype
-  int grid_d[3] = {0, 0, 0};
+  // co-resident workgroups of each kernel: by form (1 = f32, 2 = f64,
+  // 3 = mixed) and, for compression, workgroup size (8 or 16 waves)
+  int grid_c[4][2] = {};
+  int grid_d[4] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last timed kernel
   bool timed = false;
   // host <-> device pipeline
@@ -93,7 +95,13 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
                                  uint64_t payload, void* d_out, hipStream_t s, bool timed);
 inline bool decompress_failed(const Lane& l) { return rd32(l.stage + 32) == l.epoch; }
 
+inline int max_grid_c(const falcon_ctx* ctx, int form, int nw);
+inline int max_grid_d(const falcon_ctx* ctx, int form);
+
 // Frees the pipeline lanes and their buffers (pipeline.cpp).
 void pipe_release(falcon_ctx* ctx);
 
 }  // namespace falcon_host
+
+inline int falcon_host::max_grid_c(const falcon_ctx* ctx, int form, int nw) { return ctx->grid_c[form][nw == 8 ? 0 : 1]; }
+inline int falcon_host::max_grid_d(const falcon_ctx* ctx, int form) { return ctx->grid_d[form]; }

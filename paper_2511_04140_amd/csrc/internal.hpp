@@ -27,7 +27,7 @@ struct CompressSeries {
   uint64_t chunk0;
   uint64_t group0;   // index of the series' first 64-chunk group status word
   uint32_t dtype;    // 1 = f32, 2 = f64
-  uint32_t pad;
+  uint32_t idx;      // position of the series in the caller's list (lens[idx])
 };
 
 struct DecompressSeries {
@@ -36,9 +36,10 @@ struct DecompressSeries {
   uint64_t n;
   uint64_t chunk0;
   uint64_t group0;
-  uint64_t payload_bytes;
+  uint64_t payload_bytes;  // batch launches: filled on the device from the stream header
+  uint64_t in_len;         // stream bytes (batch launches)
   uint32_t dtype;
-  uint32_t pad;
+  uint32_t idx;
 };
 
 struct CompressArgs {
@@ -46,10 +47,12 @@ struct CompressArgs {
   const CompressSeries* many;    // device array, sorted by chunk0, when nseries > 1
   uint32_t nseries;
   uint32_t total_waves;
-  uint64_t total_chunks;
+  uint64_t total_chunks;  // chunks of this launch: launch chunks t0 .. t0 + total_chunks - 1
+  uint64_t t0;
   uint64_t* status;    // one word per chunk of the launch
   uint64_t* gstatus;   // one word per 64-chunk group of each series
   Ctl* ctl;
+  uint64_t* lens;      // batch launches: stream length of each series (device), else null
   uint32_t epoch;
   uint32_t pad;
 };
@@ -60,26 +63,51 @@ struct DecompressArgs {
   uint32_t nseries;
   uint32_t total_waves;
   uint64_t total_chunks;
+  uint64_t t0;
   const uint64_t* status;  // chunk offsets (exclusive prefix of the sizes)
   Ctl* ctl;
   uint32_t epoch;
-  uint32_t pad;
+  uint32_t relative;       // 1: offsets run over all series; a series subtracts its first one
 };
 
-constexpr int kCompressWaves = 16;    // wavefronts per compression workgroup
+constexpr int kCompressWaves = 16;    // default wavefronts per compression workgroup
 constexpr int kDecompressWaves = 4;   // wavefronts per decompression workgroup
 
-hipError_t launch_compress(const CompressArgs& a, int dtype, int grid, hipStream_t s);
-hipError_t launch_decompress(const DecompressArgs& a, int dtype, int grid, hipStream_t s);
+// Kernel forms: one instantiation per dtype (1 = f32, 2 = f64) and a mixed
+// one (3) that takes either dtype per series.  nw = wavefronts per
+// compression workgroup, 8 or 16.
+constexpr int kFormMixed = 3;
+hipError_t launch_compress(const CompressArgs& a, int form, int nw, int grid, hipStream_t s);
+hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s);
+// per-form entry points (one translation unit each)
+hipError_t launch_compress_f64(const CompressArgs& a, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_f32(const CompressArgs& a, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_mixed(const CompressArgs& a, int nw, int grid, hipStream_t s);
+hipError_t launch_decompress_f64(const DecompressArgs& a, int grid, hipStream_t s);
+hipError_t launch_decompress_f32(const DecompressArgs& a, int grid, hipStream_t s);
+hipError_t launch_decompress_mixed(const DecompressArgs& a, int grid, hipStream_t s);
+const void* compress_kernel_f64(int nw);
+const void* compress_kernel_f32(int nw);
+const void* compress_kernel_mixed(int nw);
+const void* decompress_kernel_f64();
+const void* decompress_kernel_f32();
+const void* decompress_kernel_mixed();
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
 // Exclusive prefix of n chunk sizes into offsets; sizes outside [lo, hi] or
-// a total other than expect store the epoch in ctl->error.  tile_tmp holds
+// a total other than expect (unless expect is UINT64_MAX) store the epoch in
+// ctl->error.  tile_tmp holds
 // scan_tiles(n) words.
 hipError_t launch_scan_sizes(const uint32_t* sizes, uint64_t n, uint32_t lo, uint32_t hi, uint64_t expect,
                              uint64_t* tile_tmp, uint64_t* offsets, Ctl* ctl, uint32_t epoch, hipStream_t s);
 uint64_t scan_tiles(uint64_t n);
+// Batch decompression, before the scan: reads every series' stream header
+// on the device, checks it against the descriptor (value count, dtype,
+// lengths) and stores its payload byte count in the descriptor; then copies
+// every series' chunk sizes into one array indexed by launch chunk.
+hipError_t launch_batch_dprep(DecompressSeries* many, uint32_t ns, uint64_t total_chunks, uint32_t* sizes_out,
+                              Ctl* ctl, uint32_t epoch, hipStream_t s);
 // Largest number of co-resident workgroups of each kernel on the device.
-int max_grid_compress(int device, int dtype);
-int max_grid_decompress(int device, int dtype);
+int max_grid_compress(int device, int form, int nw);
+int max_grid_decompress(int device, int form);
 
 }  // namespace falcon_dev

@@ -1,0 +1,42 @@
+// kernels_mixed.hip -- kernels that take series of both dtypes in one launch
+// (the wave branches on the dtype of each chunk's series), and their
+// launchers.
+#include "codec_kernels.hpp"
+
+namespace falcon_dev {
+
+__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress_mixed(
+    DecompressArgs a) {
+  __shared__ BlockLdsT<kWavesD> sm;
+  load_tables(sm.tab);
+  __syncthreads();
+  const int lane = lane_id();
+  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
+  const uint64_t w0 = (uint64_t)blockIdx.x * kWavesD + (threadIdx.x >> 6);
+  for (uint64_t t = w0; t < a.total_chunks; t += a.total_waves) {
+    const uint64_t tg = t + a.t0;
+    const DecompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    if (uniform(sd.dtype) == 2) decompress_one<TF64>(sm.tab, buf, a, sd, tg, lane);
+    else decompress_one<TF32>(sm.tab, buf, a, sd, tg, lane);
+  }
+}
+
+hipError_t launch_compress_mixed(const CompressArgs& a, int nw, int grid, hipStream_t s) {
+  if (nw == 8) hipLaunchKernelGGL(k_compress_mixed<8>, dim3(grid), dim3(64 * 8), 0, s, a);
+  else hipLaunchKernelGGL(k_compress_mixed<16>, dim3(grid), dim3(64 * 16), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_decompress_mixed(const DecompressArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_decompress_mixed, dim3(grid), dim3(64 * kWavesD), 0, s, a);
+  return hipGetLastError();
+}
+
+const void* compress_kernel_mixed(int nw) {
+  return nw == 8 ? reinterpret_cast<const void*>(&k_compress_mixed<8>)
+                 : reinterpret_cast<const void*>(&k_compress_mixed<16>);
+}
+
+const void* decompress_kernel_mixed() { return reinterpret_cast<const void*>(&k_decompress_mixed); }
+
+}  // namespace falcon_dev

@@ -69,3 +69,32 @@ def test_decimal_exponent_estimate():
             # 2^e2 = 1 / 2^-e2
             assert (k < 0 and 2 ** -e2 <= 10 ** -k and 10 ** (-k - 1) < 2 ** -e2) or \
                    (k >= 0 and False), e2
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes mirrors of falcon_series / falcon_plan_info have the C
+    layout (sizes and field offsets from a C program built against
+    falcon.h)."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2511_04140_amd import codec as C
+    src = tmp_path / "layout.c"
+    fields_s = [f for f, _ in C.Series._fields_]
+    fields_i = [f for f, _ in C.PlanInfo._fields_]
+    body = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void) {',
+            'printf("%zu %zu\\n", sizeof(falcon_series), sizeof(falcon_plan_info));']
+    for f in fields_s:
+        body.append(f'printf("%zu\\n", offsetof(falcon_series, {f}));')
+    for f in fields_i:
+        body.append(f'printf("%zu\\n", offsetof(falcon_plan_info, {f}));')
+    body.append("return 0; }")
+    src.write_text("\n".join(body))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(C.Series) and vals[1] == ctypes.sizeof(C.PlanInfo)
+    offs = vals[2:]
+    assert offs[:len(fields_s)] == [getattr(C.Series, f).offset for f in fields_s]
+    assert offs[len(fields_s):] == [getattr(C.PlanInfo, f).offset for f in fields_i]
