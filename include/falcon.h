@@ -198,6 +198,68 @@ falcon_status falcon_plan_describe(const falcon_plan* p, falcon_plan_info* info)
 
 void falcon_plan_destroy(falcon_plan* p);
 
+/* ---- Serving: a request loop with continuous batching ------------------
+ * Clients submit compress and decompress requests on device-resident
+ * inputs; a worker thread admits them in arrival order as output memory
+ * frees up in a device pool of hbm_budget bytes, groups admitted requests of
+ * one kind into batch launches (as falcon_compress_batch /
+ * falcon_decompress_batch) on up to `lanes` streams, and keeps admitting and
+ * launching arrivals while earlier batches run, so their work overlaps on
+ * the device.  Each request's output is byte-identical to the one-series
+ * call on it, alone or in any mix.  lanes = 1, max_batch = 1 gives the plain
+ * one-request-per-launch FIFO. */
+typedef struct falcon_server falcon_server;
+
+typedef struct falcon_server_opts {
+  size_t hbm_budget;  /* bytes of the output pool (0: 64 GiB) */
+  void* pool;         /* optional caller-owned device memory of hbm_budget bytes to use as the pool
+                         (256-byte aligned; kept by the caller); NULL: the server allocates it */
+  int lanes;          /* concurrent batch launches, 1..32 (0: 4) */
+  int max_batch;      /* requests per batch launch (0: 256) */
+} falcon_server_opts;
+
+typedef struct falcon_request {
+  falcon_op op;
+  const void* d_in;   /* device: n values (compress) or a stream of in_len bytes holding n values */
+  size_t n;
+  size_t in_len;
+  falcon_dtype dtype;
+  uint64_t tag;       /* returned with the completion */
+} falcon_request;
+
+typedef struct falcon_completion {
+  uint64_t tag;
+  falcon_status status;
+  void* d_out;        /* in the server's pool: the stream (compress) or the values; null on error */
+  size_t out_len;     /* stream bytes (compress) or values (decompress) */
+  double submit_us, admit_us, complete_us;  /* times since the server was created */
+} falcon_completion;
+
+/* Creates a server on ctx (opts may be NULL).  The input buffers of a
+ * request must stay valid until its completion is polled.  The context must
+ * not be destroyed before the server. */
+falcon_status falcon_server_create(falcon_ctx* ctx, const falcon_server_opts* opts, falcon_server** out);
+
+/* Queues a request (thread-safe; returns at once).  A request whose output
+ * is larger than the whole pool completes with FALCON_ERR_OUT_OF_MEMORY; a
+ * bad descriptor completes with the status the batch call would return. */
+falcon_status falcon_server_submit(falcon_server* s, const falcon_request* r);
+
+/* Moves up to max completions into out, waiting up to wait_ms for the
+ * first; returns how many were moved. */
+size_t falcon_server_poll(falcon_server* s, falcon_completion* out, size_t max, int wait_ms);
+
+/* Returns a completion's output buffer to the pool. */
+falcon_status falcon_server_release(falcon_server* s, void* d_out);
+
+/* Requests submitted and not yet completed. */
+uint64_t falcon_server_in_flight(const falcon_server* s);
+
+/* Stops the worker after the work it can still do (requests that cannot be
+ * admitted any more complete with FALCON_ERR_OUT_OF_MEMORY) and frees the
+ * pool, including unreleased outputs. */
+void falcon_server_destroy(falcon_server* s);
+
 /* Parses a stream header held in host memory (len >= 32 bytes) and returns
  * the value count and dtype.  FALCON_ERR_CORRUPT_STREAM if the header is not
  * a version-1 Falcon header. */

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfalcon.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "kernels_f64.hip", "kernels_f32.hip", "kernels_mixed.hip", "kernels_common.hip",
-    "api.cpp", "pipeline.cpp", "batch.cpp")]
+    "api.cpp", "pipeline.cpp", "batch.cpp", "serve.cpp")]
 ARCH = os.environ.get("FALCON_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

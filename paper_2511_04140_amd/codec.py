@@ -43,6 +43,22 @@ class PlanInfo(ctypes.Structure):
                 ("graph", ctypes.c_int), ("total_chunks", ctypes.c_uint64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("pool", ctypes.c_void_p), ("lanes", ctypes.c_int),
+                ("max_batch", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("d_in", ctypes.c_void_p), ("n", ctypes.c_size_t),
+                ("in_len", ctypes.c_size_t), ("dtype", ctypes.c_int), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("d_out", ctypes.c_void_p),
+                ("out_len", ctypes.c_size_t), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("complete_us", ctypes.c_double)]
+
+
 OP_COMPRESS = 0
 OP_DECOMPRESS = 1
 PLAN_TUNE = 1
@@ -89,6 +105,18 @@ def _load():
     L.falcon_plan_describe.restype = i
     L.falcon_plan_destroy.argtypes = [vp]
     L.falcon_plan_destroy.restype = None
+    L.falcon_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.falcon_server_create.restype = i
+    L.falcon_server_submit.argtypes = [vp, ctypes.POINTER(Request)]
+    L.falcon_server_submit.restype = i
+    L.falcon_server_poll.argtypes = [vp, ctypes.POINTER(Completion), sz, i]
+    L.falcon_server_poll.restype = sz
+    L.falcon_server_release.argtypes = [vp, vp]
+    L.falcon_server_release.restype = i
+    L.falcon_server_in_flight.argtypes = [vp]
+    L.falcon_server_in_flight.restype = ctypes.c_uint64
+    L.falcon_server_destroy.argtypes = [vp]
+    L.falcon_server_destroy.restype = None
     L.falcon_status_str.argtypes = [i]
     L.falcon_status_str.restype = ctypes.c_char_p
     return L
@@ -328,6 +356,71 @@ class Plan:
         if self._p:
             lib().falcon_plan_destroy(self._p)
             self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The request loop (falcon_server) with its output pool in a torch
+    device tensor, so that completions can be viewed as tensors."""
+
+    def __init__(self, codec: Codec, hbm_budget: int = 1 << 30, lanes: int = 4, max_batch: int = 256):
+        self.codec = codec
+        self.pool = torch.empty(hbm_budget, dtype=torch.uint8, device=codec.device)
+        opts = ServerOpts(hbm_budget, self.pool.data_ptr(), lanes, max_batch)
+        self._s = ctypes.c_void_p()
+        st = lib().falcon_server_create(codec._ctx, ctypes.byref(opts), ctypes.byref(self._s))
+        if st != 0:
+            raise FalconError(st, "falcon_server_create")
+        self._buf = (Completion * 1024)()
+
+    def submit_compress(self, x: torch.Tensor, tag: int):
+        r = Request(OP_COMPRESS, x.data_ptr() if x.numel() else None, x.numel(), 0, _dtype_code(x.dtype), tag)
+        st = lib().falcon_server_submit(self._s, ctypes.byref(r))
+        if st != 0:
+            raise FalconError(st, "falcon_server_submit")
+
+    def submit_decompress(self, stream: torch.Tensor, n: int, dtype: torch.dtype, tag: int):
+        r = Request(OP_DECOMPRESS, stream.data_ptr(), n, stream.numel(), _dtype_code(dtype), tag)
+        st = lib().falcon_server_submit(self._s, ctypes.byref(r))
+        if st != 0:
+            raise FalconError(st, "falcon_server_submit")
+
+    def poll(self, wait_ms: int = 0):
+        """Completions as dicts (tag, status, offset into the pool, out_len,
+        submit/admit/complete times in microseconds)."""
+        k = lib().falcon_server_poll(self._s, self._buf, len(self._buf), wait_ms)
+        base = self.pool.data_ptr()
+        out = []
+        for i in range(k):
+            c = self._buf[i]
+            out.append({"tag": c.tag, "status": c.status, "d_out": c.d_out,
+                        "offset": (c.d_out - base) if c.d_out else None, "out_len": c.out_len,
+                        "submit_us": c.submit_us, "admit_us": c.admit_us, "complete_us": c.complete_us})
+        return out
+
+    def view(self, comp: dict, dtype: torch.dtype = torch.uint8) -> torch.Tensor:
+        """The completion's output as a tensor (a view of the pool)."""
+        nbytes = comp["out_len"] * (torch.empty(0, dtype=dtype).element_size() if dtype != torch.uint8 else 1)
+        return self.pool[comp["offset"]: comp["offset"] + nbytes].view(dtype)
+
+    def release(self, comp: dict):
+        if comp["d_out"]:
+            st = lib().falcon_server_release(self._s, ctypes.c_void_p(comp["d_out"]))
+            if st != 0:
+                raise FalconError(st, "falcon_server_release")
+
+    def in_flight(self) -> int:
+        return lib().falcon_server_in_flight(self._s)
+
+    def close(self):
+        if self._s:
+            lib().falcon_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
 
     def __del__(self):
         try:

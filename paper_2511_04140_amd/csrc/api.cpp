@@ -217,6 +217,8 @@ void falcon_destroy(falcon_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   pipe_release(ctx);
+  if (ctx->main.stream) (void)hipStreamSynchronize(ctx->main.stream);
+  batch_free(ctx->batch);
   lane_free(ctx->main);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

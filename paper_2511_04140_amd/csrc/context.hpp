@@ -59,6 +59,47 @@ struct PipeLane {
   uint64_t c0 = 0, nchunks = 0, nvals = 0, cs = 0, dst = 0;
 };
 
+// ---- batch launches (batch.cpp) -------------------------------------------
+// Launch geometry of a batch: one launch per dtype (split) or one over both,
+// wavefronts per compression workgroup, grid as a percentage of the
+// co-resident workgroups.
+struct BatchGeom {
+  int split = 1;
+  int nw = falcon_dev::kCompressWaves;
+  int grid_pct = 100;
+};
+
+// Where a batch's series sit in launch-chunk space (float64 series first).
+struct BatchLayout {
+  int op = 0;
+  size_t count = 0;
+  uint64_t total = 0, t64 = 0, groups = 0;
+  bool has64 = false, has32 = false;
+  falcon_dev::CompressSeries one_c{};
+  falcon_dev::DecompressSeries one_d{};
+  size_t desc_bytes = 0;
+};
+
+// Device and pinned scratch of batch launches; grows on demand.  Scratch
+// that a recorded graph uses must not grow afterwards.
+struct BatchScratch {
+  void* many = nullptr;          // device descriptors
+  size_t many_cap = 0;
+  uint8_t* h_desc = nullptr;     // pinned host copy of the descriptors
+  size_t h_desc_cap = 0;
+  uint64_t* status = nullptr;
+  size_t status_cap = 0;
+  uint64_t* gstatus = nullptr;
+  size_t gstatus_cap = 0;
+  uint32_t* sizes = nullptr;     // decompression: gathered chunk sizes
+  size_t sizes_cap = 0;
+  falcon_dev::Ctl* ctl = nullptr;
+  uint64_t* lens = nullptr;      // device stream lengths (compression)
+  size_t lens_cap = 0;
+  uint64_t* h_lens = nullptr;    // pinned: lengths, then the error word
+  size_t h_lens_cap = 0;
+};
+
 }  // namespace falcon_host
 
 struct falcon_ctx {
@@ -76,6 +117,8 @@ struct falcon_ctx {
   size_t pipe_buf_bytes = 0;     // bytes of each g_in / g_out / p_in / p_out
   bool pipe_staging = false;     // p_in / p_out allocated
   std::vector<falcon_host::PipeLane> pipe;
+  // one-shot batch calls
+  falcon_host::BatchScratch batch;
 };
 
 namespace falcon_host {
@@ -100,6 +143,21 @@ inline int max_grid_d(const falcon_ctx* ctx, int form);
 
 // Frees the pipeline lanes and their buffers (pipeline.cpp).
 void pipe_release(falcon_ctx* ctx);
+
+falcon_status batch_check(int op, const falcon_series& d);
+// Lays the series out, writes their descriptors into the pinned copy and
+// grows the device scratch to fit (waiting for `s` first if it grows).
+falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size_t count, BatchLayout& L,
+                           hipStream_t st);
+// Enqueues one run: descriptor upload (if upload), clearing fills, the
+// launches, and the copy of the lengths or the error word to pinned memory.
+falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchLayout& L, const BatchGeom& g,
+                            hipStream_t s, bool upload);
+// After the run has completed: the error status, and each dst[i].out_len
+// (dst may be null; src holds the series the layout was made from).
+falcon_status batch_result(const BatchScratch& b, const BatchLayout& L, const falcon_series* src,
+                           falcon_series* dst);
+void batch_free(BatchScratch& b);
 
 }  // namespace falcon_host
 

@@ -72,29 +72,27 @@ def test_decimal_exponent_estimate():
 
 
 def test_struct_layouts_match_the_binding(tmp_path):
-    """The ctypes mirrors of falcon_series / falcon_plan_info have the C
-    layout (sizes and field offsets from a C program built against
-    falcon.h)."""
+    """The ctypes mirrors of the ABI's structs have the C layout (sizes and
+    field offsets from a C program built against falcon.h)."""
     import subprocess
     import sys
     sys.path.insert(0, ROOT)
     from paper_2511_04140_amd import codec as C
-    src = tmp_path / "layout.c"
-    fields_s = [f for f, _ in C.Series._fields_]
-    fields_i = [f for f, _ in C.PlanInfo._fields_]
-    body = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void) {',
-            'printf("%zu %zu\\n", sizeof(falcon_series), sizeof(falcon_plan_info));']
-    for f in fields_s:
-        body.append(f'printf("%zu\\n", offsetof(falcon_series, {f}));')
-    for f in fields_i:
-        body.append(f'printf("%zu\\n", offsetof(falcon_plan_info, {f}));')
+    pairs = [(C.Series, "falcon_series"), (C.PlanInfo, "falcon_plan_info"),
+             (C.ServerOpts, "falcon_server_opts"), (C.Request, "falcon_request"),
+             (C.Completion, "falcon_completion")]
+    body = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void) {']
+    want = []
+    for cls, cname in pairs:
+        body.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            body.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(cls, f).offset)
     body.append("return 0; }")
+    src = tmp_path / "layout.c"
     src.write_text("\n".join(body))
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    vals = [int(v) for v in out]
-    assert vals[0] == ctypes.sizeof(C.Series) and vals[1] == ctypes.sizeof(C.PlanInfo)
-    offs = vals[2:]
-    assert offs[:len(fields_s)] == [getattr(C.Series, f).offset for f in fields_s]
-    assert offs[len(fields_s):] == [getattr(C.PlanInfo, f).offset for f in fields_i]
+    assert [int(v) for v in out] == want
