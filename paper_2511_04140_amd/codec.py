@@ -335,12 +335,16 @@ class Plan:
         if st != 0:
             raise FalconError(st, "falcon_plan_create")
 
-    def run(self, stream=None):
-        """Runs the plan; returns the outputs (streams trimmed to length)."""
+    def run(self, stream=None, fetch: bool = True):
+        """Runs the plan; returns the outputs (streams trimmed to length), or
+        None with fetch=False (no per-series lengths are read back into
+        Python, which for thousands of series costs more than the launch)."""
         h = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
-        st = lib().falcon_plan_run(self._p, self.descs, h)
+        st = lib().falcon_plan_run(self._p, self.descs if fetch else None, h)
         if st != 0:
             raise FalconError(st, "falcon_plan_run")
+        if not fetch:
+            return None
         if self.op == OP_COMPRESS:
             return [v[: self.descs[i].out_len] for i, v in enumerate(self.views)]
         return self.views

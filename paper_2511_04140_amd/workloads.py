@@ -175,3 +175,52 @@ def decimal_f32(n: int, seed: int, places: int, magnitude: float = 10.0) -> np.n
     x = rng.uniform(-magnitude, magnitude, n)
     m = np.rint(x * 10.0 ** places).astype(np.float32)
     return m / np.float32(10.0 ** places) + np.float32(0.0)
+
+
+def _sensor_values(rng, n: int, d: int, phase: int) -> np.ndarray:
+    """100 sin(2 pi t / 1e4) + random walk (sigma 0.05), rounded to d places."""
+    t = (np.arange(n) + phase) % 10000
+    walk = np.cumsum(rng.standard_normal(n, dtype=np.float32).astype(np.float64) * 0.05)
+    x = 100.0 * _SIN_1E4[t] + walk
+    s = _POW10[d]
+    return np.rint(x * s) / s + 0.0
+
+
+def batch_series(count: int = 10000, seed: int = 4, lo: int = 1024, hi: int = 369_000,
+                 f64_share: float = 0.6, max_places: int = 6) -> list:
+    """Independent series for batched launches: lengths log-uniform on
+    [lo, hi] values, a shuffled f64_share of them float64 and the rest
+    float32, d ~ U{0..max_places} decimal places per series, sensor-like
+    values without outliers or specials.  With the defaults the expected
+    total is about 4 GB (10,000 x 62,500 values x 6.4 bytes)."""
+    rng = np.random.default_rng([seed, 0])
+    n64 = int(round(count * f64_share))
+    is64 = np.zeros(count, bool)
+    is64[rng.permutation(count)[:n64]] = True
+    lens = np.exp(rng.uniform(np.log(lo), np.log(hi), count)).astype(np.int64)
+    places = rng.integers(0, max_places + 1, count)
+
+    def one(i):
+        r = np.random.default_rng([seed, 1, i])
+        v = _sensor_values(r, int(lens[i]), int(places[i]), int(r.integers(0, 10000)))
+        return v if is64[i] else v.astype(np.float32)
+
+    with _pool() as ex:
+        return list(ex.map(one, range(count)))
+
+
+def serving_payloads(count: int = 256, seed: int = 5, lo_bytes: int = 4096, hi_bytes: int = 64 << 20) -> list:
+    """Request payloads for the serving loop: byte sizes log-uniform on
+    [lo_bytes, hi_bytes], dtype float64 or float32 with equal odds, content
+    as sensor_f64 (segments of 1-6 places, 1% outliers, specials at 1e-5)."""
+    rng = np.random.default_rng([seed, 0])
+    sizes = np.exp(rng.uniform(np.log(lo_bytes), np.log(hi_bytes), count)).astype(np.int64)
+    f64 = rng.random(count) < 0.5
+    out = []
+    for i in range(count):
+        es = 8 if f64[i] else 4
+        n = max(1, int(sizes[i]) // es)
+        v = sensor_f64(n, seed=seed * 1000 + i)
+        with np.errstate(invalid="ignore", over="ignore"):
+            out.append(v if f64[i] else v.astype(np.float32))
+    return out
