@@ -45,6 +45,8 @@ void lane_free(Lane& l) {
   if (l.stream) (void)hipStreamSynchronize(l.stream);
   if (l.status) (void)hipFree(l.status);
   if (l.gstatus) (void)hipFree(l.gstatus);
+  if (l.meta) (void)hipFree(l.meta);
+  if (l.gsizes) (void)hipFree(l.gsizes);
   if (l.ctl) (void)hipFree(l.ctl);
   if (l.stage) (void)hipHostFree(l.stage);
   if (l.stream) (void)hipStreamDestroy(l.stream);
@@ -52,6 +54,23 @@ void lane_free(Lane& l) {
 }
 
 namespace {
+
+// Grows a device array to at least n elements (contents undefined).
+template <class P>
+falcon_status grow_raw(P** arr, size_t* cap, uint64_t n, hipStream_t s) {
+  if (n <= *cap && *arr) return FALCON_OK;
+  size_t c = *cap ? *cap : 1024;
+  while (c < n) c *= 2;
+  if (*arr) {
+    if (hipStreamSynchronize(s) != hipSuccess) return FALCON_ERR_DEVICE;
+    (void)hipFree(*arr);
+  }
+  *arr = nullptr;
+  *cap = 0;
+  if (hipMalloc(reinterpret_cast<void**>(arr), c * sizeof(P)) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
+  *cap = c;
+  return FALCON_OK;
+}
 
 // Grows a zeroed status array to at least n words.
 falcon_status grow_zeroed(uint64_t** arr, size_t* cap, uint64_t n, hipStream_t s) {
@@ -92,10 +111,14 @@ int grid_for(int max_grid, uint64_t nchunks, int waves_per_block) {
 
 }  // namespace
 
+// Two-pass compression: size pass, scan of the sizes, write pass (see
+// codec_kernels.hpp).  The lane's status array receives the offsets.
 falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
                                hipStream_t s, bool timed) {
   const uint64_t nc = chunks_of(n);
-  falcon_status st = prepare_launch(l, nc ? nc : 1, groups_of(nc) + 1, s);
+  falcon_status st = prepare_launch(l, nc ? nc : 1, scan_tiles(nc) + 1, s);
+  if (st == FALCON_OK) st = grow_raw(&l.meta, &l.meta_cap, nc ? nc : 1, s);
+  if (st == FALCON_OK) st = grow_raw(&l.gsizes, &l.gsizes_cap, nc ? nc : 1, s);
   if (st != FALCON_OK) return st;
   CompressArgs a{};
   a.one.in = d_in;
@@ -111,14 +134,26 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.gstatus = l.gstatus;
   a.ctl = l.ctl;
   a.lens = nullptr;
+  a.meta = l.meta;
+  a.gsizes = l.gsizes;
+  a.offsets = l.status;
   a.epoch = l.epoch;
-  const int grid = grid_for(max_grid_c(ctx, dt, kCompressWaves), nc, kCompressWaves);
-  a.total_waves = (uint32_t)(grid * kCompressWaves);
+  a.relative = 0;
+  const int g1 = grid_for(max_grid_c(ctx, dt, 1, kCompressWaves), nc, kCompressWaves);
+  const int g2 = grid_for(max_grid_c(ctx, dt, 2, kCompressWaves), nc, kCompressWaves);
   if (timed) {
     ctx->timed = false;
     if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
   }
-  if ((st = dev_err(launch_compress(a, (int)dt, kCompressWaves, grid, s))) != FALCON_OK) return st;
+  if (nc) {
+    a.total_waves = (uint32_t)(g1 * kCompressWaves);
+    if ((st = dev_err(launch_compress(a, (int)dt, 1, kCompressWaves, g1, s))) != FALCON_OK) return st;
+    if ((st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.gstatus, l.status, l.ctl, l.epoch, s))) !=
+        FALCON_OK)
+      return st;
+  }
+  a.total_waves = (uint32_t)(g2 * kCompressWaves);
+  if ((st = dev_err(launch_compress(a, (int)dt, 2, kCompressWaves, g2, s))) != FALCON_OK) return st;
   if (timed) {
     if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
     ctx->timed = true;
@@ -205,8 +240,10 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
     return FALCON_ERR_DEVICE;
   }
   for (int form = 1; form <= 3; ++form) {
-    ctx->grid_c[form][0] = max_grid_compress(device, form, 8);
-    ctx->grid_c[form][1] = max_grid_compress(device, form, 16);
+    for (int pass = 0; pass < 3; ++pass) {
+      ctx->grid_c[form][pass][0] = max_grid_compress(device, form, pass, 8);
+      ctx->grid_c[form][pass][1] = max_grid_compress(device, form, pass, 16);
+    }
     ctx->grid_d[form] = max_grid_decompress(device, form);
   }
   *out = ctx;

@@ -3,17 +3,18 @@
 //
 // Every chunk of every series gets a launch chunk index t: the float64
 // series come first, then the float32 ones, each series' chunks
-// consecutive.  A launch hands chunks out in t order (compression tickets,
-// decompression striding); each series' look-back stops at its own first
+// consecutive.  Waves take chunks by static striding over t; each series'
+// offsets are the scan of all chunk sizes minus the offset of its own first
 // chunk, so series are independent and each output is byte-identical to a
 // one-series call.  Two launch forms exist: split (one launch per dtype,
 // each over its own contiguous range of t) and mixed (one launch over all
 // of t, the wave branching on the dtype of the chunk's series).
 //
-// A run never depends on host state beyond its descriptors: the status
-// words and the control block are cleared by fill kernels at the start of
-// every run (no memset nodes in a recorded graph) and the launch epoch is
-// fixed.
+// Compression runs in two passes over all series (size pass, one scan of
+// all chunk sizes, write pass; see codec_kernels.hpp), so no chunk waits on
+// another.  A run never depends on host state beyond its descriptors: the
+// control block is cleared by a fill kernel at the start of a decompression
+// run (no memset nodes in a recorded graph) and the launch epoch is fixed.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -54,8 +55,8 @@ falcon_status grow(P** p, size_t* cap, size_t need, size_t elem, bool pinned, hi
   return FALCON_OK;
 }
 
-int grid_of(const falcon_ctx* ctx, const BatchGeom& g, int form, uint64_t chunks, bool compress) {
-  const int maxg = compress ? max_grid_c(ctx, form, g.nw) : max_grid_d(ctx, form);
+int grid_of(const falcon_ctx* ctx, const BatchGeom& g, int form, int pass, uint64_t chunks, bool compress) {
+  const int maxg = compress ? max_grid_c(ctx, form, pass, g.nw) : max_grid_d(ctx, form);
   int grid = (int)((int64_t)maxg * g.grid_pct / 100);
   if (grid < 1) grid = 1;
   const int per = compress ? g.nw : kDecompressWaves;
@@ -138,14 +139,16 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
   }
   L.total = t;
   L.groups = g;
-  const size_t gwords = (op == FALCON_OP_COMPRESS ? g : scan_tiles(t)) + 1;
+  const size_t gwords = scan_tiles(t) + 1;
   if ((r = grow(&b.many, &b.many_cap, L.desc_bytes, 1, false, st)) != FALCON_OK ||
       (r = grow(&b.status, &b.status_cap, t ? t : 1, 8, false, st)) != FALCON_OK ||
       (r = grow(&b.gstatus, &b.gstatus_cap, gwords, 8, false, st)) != FALCON_OK ||
       (r = grow(&b.lens, &b.lens_cap, count, 8, false, st)) != FALCON_OK ||
       (r = grow(&b.h_lens, &b.h_lens_cap, count + 1, 8, true, st)) != FALCON_OK)
     return r;
-  if (op == FALCON_OP_DECOMPRESS && (r = grow(&b.sizes, &b.sizes_cap, t ? t : 1, 4, false, st)) != FALCON_OK)
+  if ((r = grow(&b.sizes, &b.sizes_cap, t ? t : 1, 4, false, st)) != FALCON_OK) return r;
+  if (op == FALCON_OP_COMPRESS && (r = grow(&b.meta, &b.meta_cap, t ? t : 1, sizeof(ChunkMeta), false, st)) !=
+                                      FALCON_OK)
     return r;
   if (!b.ctl) {
     if (hipMalloc(&b.ctl, 64) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
@@ -160,12 +163,6 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
   if (upload && (st = dev_err(hipMemcpyAsync(b.many, b.h_desc, L.desc_bytes, hipMemcpyHostToDevice, s))) !=
                     FALCON_OK)
     return st;
-  // clear status words and the control block (ticket, exit counter, error)
-  const uint64_t gwords = (L.op == FALCON_OP_COMPRESS ? L.groups : scan_tiles(L.total)) + 1;
-  if ((st = dev_err(launch_fill_u64(b.status, L.total ? L.total : 1, 0, s))) != FALCON_OK ||
-      (st = dev_err(launch_fill_u64(b.gstatus, gwords, 0, s))) != FALCON_OK ||
-      (st = dev_err(launch_fill_u64(reinterpret_cast<uint64_t*>(b.ctl), 2, 0, s))) != FALCON_OK)
-    return st;
   struct Part { int form; uint64_t t0, chunks; };
   Part parts[2];
   int np = 0;
@@ -176,25 +173,39 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     if (L.has32) parts[np++] = {1, L.t64, L.total - L.t64};
   }
   if (L.op == FALCON_OP_COMPRESS) {
-    if (np == 0) parts[np++] = {2, 0, 0};  // only empty series: one launch writes their headers
-    for (int i = 0; i < np; ++i) {
-      CompressArgs a{};
-      a.one = L.one_c;
-      a.many = static_cast<const CompressSeries*>(b.many);
-      a.nseries = (uint32_t)L.count;
-      a.total_chunks = parts[i].chunks;
-      a.t0 = parts[i].t0;
-      a.status = b.status;
-      a.gstatus = b.gstatus;
-      a.ctl = b.ctl;
-      a.lens = b.lens;
-      a.epoch = kBatchEpoch;
-      const int grid = grid_of(ctx, g, parts[i].form, parts[i].chunks, true);
-      a.total_waves = (uint32_t)(grid * g.nw);
-      if ((st = dev_err(launch_compress(a, parts[i].form, g.nw, grid, s))) != FALCON_OK) return st;
+    // two passes over all series: sizes, one scan over all chunks, writes
+    if (np == 0) parts[np++] = {2, 0, 0};  // only empty series: the write pass writes their headers
+    CompressArgs a{};
+    a.one = L.one_c;
+    a.many = static_cast<const CompressSeries*>(b.many);
+    a.nseries = (uint32_t)L.count;
+    a.status = b.status;
+    a.gstatus = b.gstatus;
+    a.ctl = b.ctl;
+    a.lens = b.lens;
+    a.meta = b.meta;
+    a.gsizes = b.sizes;
+    a.offsets = b.status;
+    a.epoch = kBatchEpoch;
+    a.relative = 1;
+    for (int pass = 1; pass <= 2; ++pass) {
+      for (int i = 0; i < np; ++i) {
+        if (pass == 1 && parts[i].chunks == 0) continue;
+        a.total_chunks = parts[i].chunks;
+        a.t0 = parts[i].t0;
+        const int grid = grid_of(ctx, g, parts[i].form, pass, parts[i].chunks, true);
+        a.total_waves = (uint32_t)(grid * g.nw);
+        if ((st = dev_err(launch_compress(a, parts[i].form, pass, g.nw, grid, s))) != FALCON_OK) return st;
+      }
+      if (pass == 1 && L.total &&
+          (st = dev_err(launch_scan_sizes(b.sizes, L.total, 0, ~0u, ~0ull, b.gstatus, b.status, b.ctl, kBatchEpoch,
+                                          s))) != FALCON_OK)
+        return st;
     }
     return dev_err(hipMemcpyAsync(b.h_lens, b.lens, L.count * 8, hipMemcpyDeviceToHost, s));
   }
+  // clear the control block (error word) of decompression
+  if ((st = dev_err(launch_fill_u64(reinterpret_cast<uint64_t*>(b.ctl), 2, 0, s))) != FALCON_OK) return st;
   // decompression: headers and sizes, one scan over all chunks, kernels
   DecompressSeries* many = static_cast<DecompressSeries*>(b.many);
   if ((st = dev_err(launch_batch_dprep(many, (uint32_t)L.count, L.total, b.sizes, b.ctl, kBatchEpoch, s))) !=
@@ -213,7 +224,7 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     a.ctl = b.ctl;
     a.epoch = kBatchEpoch;
     a.relative = 1;
-    const int grid = grid_of(ctx, g, parts[i].form, parts[i].chunks, false);
+    const int grid = grid_of(ctx, g, parts[i].form, 0, parts[i].chunks, false);
     a.total_waves = (uint32_t)(grid * kDecompressWaves);
     if ((st = dev_err(launch_decompress(a, parts[i].form, grid, s))) != FALCON_OK) return st;
   }
@@ -238,6 +249,7 @@ void batch_free(BatchScratch& b) {
   if (b.status) (void)hipFree(b.status);
   if (b.gstatus) (void)hipFree(b.gstatus);
   if (b.sizes) (void)hipFree(b.sizes);
+  if (b.meta) (void)hipFree(b.meta);
   if (b.ctl) (void)hipFree(b.ctl);
   if (b.lens) (void)hipFree(b.lens);
   if (b.h_lens) (void)hipHostFree(b.h_lens);

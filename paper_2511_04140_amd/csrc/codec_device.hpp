@@ -65,9 +65,9 @@ struct __attribute__((aligned(16))) LdsTables {
 template <int NW>
 struct __attribute__((aligned(16))) BlockLdsT {
   LdsTables tab;
-  uint32_t slot_next;     // next ticket slot of this workgroup
-  uint32_t ring_round[8]; // round whose batch index sits in ring_batch
-  uint32_t ring_batch[8];
+  uint32_t slot_next;      // next ticket slot of this workgroup
+  uint32_t ring_round[16]; // round whose batch index sits in ring_batch
+  uint32_t ring_batch[16];
   uint32_t pad[3];
   uint4 wave[NW][kWaveLds / 16];
 };

@@ -286,21 +286,20 @@ struct ChunkPlanes {
   uint32_t w;
 };
 
-// a2-a7: decimal places and case, Eq. 3 and Eq. 4, bit width, transpose.
-// vb is consumed (free for the next chunk's loads when this returns).
+// a4-a7 once the chunk's case is known (cp.A, cp.B set): Eq. 3, Eq. 4, bit
+// width, transpose.  vb is consumed (free for the next chunk's loads when
+// this returns).
 template <class T>
-__device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
-                                               int lane_in, ChunkPlanes& cp) {
+__device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t* buf,
+                                                   const typename T::U (&vb)[17], int lane_in, bool case1,
+                                                   ChunkPlanes& cp) {
   using U = typename T::U;
   using F = typename T::F;
   // An opaque copy of the lane index keeps the compiler from hoisting the
-  // per-lane address arithmetic out of the ticket loop, where it would stay
+  // per-lane address arithmetic out of the chunk loop, where it would stay
   // live (and spill) across every chunk.
   int lane = lane_in;
   asm volatile("" : "+v"(lane));
-
-  bool case1;
-  decide_case<T>(sm, vb, cp.A, cp.B, case1);
 
   // a4: Eq. 3 -> g, written to LDS in skewed natural order
   U* g = reinterpret_cast<U*>(buf);
@@ -364,16 +363,25 @@ __device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf
   if constexpr (sizeof(U) == 8) xpose16(cp.hi);
 }
 
-// a8-a11: row schemes and sizes, look-back, payload assembly and write-out.
+// a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
 template <class T>
-__device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries& sd, uint64_t c, uint64_t nc,
-                                              uint64_t t, uint64_t* status, uint64_t* gstatus, uint32_t epoch,
-                                              uint64_t* lens, int lane_in, const ChunkPlanes& cp) {
-  int lane = lane_in;  // opaque, see compress_front
-  asm volatile("" : "+v"(lane));
+__device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
+                                               int lane, ChunkPlanes& cp) {
+  bool case1;
+  decide_case<T>(sm, vb, cp.A, cp.B, case1);
+  compress_transform<T>(sm, buf, vb, lane, case1, cp);
+}
+
+// a8-a9: per-row non-zero byte counts (sparse iff more than 16 of the 128
+// bytes are zero; ties dense), scheme flags and the chunk size.
+struct ChunkStats {
+  uint64_t flags;  // bit p set: plane p is written dense
+  uint32_t S;
+};
+
+template <class T>
+__device__ __forceinline__ ChunkStats chunk_stats(const ChunkPlanes& cp) {
   const uint32_t w = cp.w;
-  // a8-a9: per-row non-zero byte counts (sparse iff more than 16 of the 128
-  // bytes are zero; ties dense), scheme flags and the chunk size.
   uint64_t flags = 0;
   uint32_t rows = 0;
   for_planes_down<T::W - 1>([&](auto pc) {
@@ -387,15 +395,23 @@ __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries
       rows += dense ? 128u : 16u + nnz;
     }
   });
+  ChunkStats st;
+  st.flags = flags;
+  st.S = 3 + T::ZB + ((w + 7) >> 3) + rows;
+  return st;
+}
+
+// a11 (first half): the chunk payload (header bytes, scheme flags, rows) in
+// the wave's LDS buffer at offset 0, followed by zeroed slack so that the
+// aligned reads of copy_payload see defined bytes.
+template <class T>
+__device__ __forceinline__ void assemble_payload(uint8_t* buf, const ChunkPlanes& cp, uint64_t flags, uint32_t S,
+                                                 int lane_in) {
+  int lane = lane_in;  // opaque, see compress_transform
+  asm volatile("" : "+v"(lane));
+  const uint32_t w = cp.w;
   const uint32_t nflag = (w + 7) >> 3;
   const uint32_t hlen = 3 + T::ZB + nflag;
-  const uint32_t S = hlen + rows;
-
-  // a10 (first half): publish the chunk size and issue the look-back reads
-  const LookbackSamples smp = lookback_begin(status, gstatus, t, c, sd.group0, S, epoch, lane);
-
-  // a11 (first half): assemble the payload in LDS at offset 0 while the
-  // look-back reads are in flight.
   if (lane < (int)hlen) {
     uint32_t byte;
     if (lane == 0) byte = (uint32_t)cp.A;
@@ -429,17 +445,12 @@ __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries
       }
     }
   });
-  // zero the slack after the payload so that the aligned reads below see
-  // defined bytes
   if (lane < 8) reinterpret_cast<uint32_t*>(buf)[((S + 3) >> 2) + lane] = 0u;
-  wave_lds_sync();
+}
 
-  // a10 (second half): exclusive prefix of the chunk sizes
-  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, smp);
-
-  // a11 (second half): copy the payload to payload + off with aligned
-  // 16-byte stores; byte stores only in the first and last block.
-  uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
+// a11 (second half): copies the S payload bytes from LDS to dst with aligned
+// 16-byte stores; byte stores only in the first and last block.
+__device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dst, uint32_t S, int lane) {
   const uint32_t ph = (uint32_t)((uintptr_t)dst & 15u);
   uint8_t* dal = dst - ph;
   const uint32_t nblk = (ph + S + 15) >> 4;
@@ -467,6 +478,26 @@ __device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries
       for (uint32_t b = from; b < to; ++b) dal[b] = buf[b - ph];
     }
   }
+}
+
+// a8-a11 in one pass: row schemes and sizes, look-back, payload assembly
+// and write-out.
+template <class T>
+__device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries& sd, uint64_t c, uint64_t nc,
+                                              uint64_t t, uint64_t* status, uint64_t* gstatus, uint32_t epoch,
+                                              uint64_t* lens, int lane_in, const ChunkPlanes& cp) {
+  int lane = lane_in;  // opaque, see compress_transform
+  asm volatile("" : "+v"(lane));
+  const ChunkStats st = chunk_stats<T>(cp);
+  const uint32_t S = st.S;
+  // a10 (first half): publish the chunk size and issue the look-back reads
+  const LookbackSamples smp = lookback_begin(status, gstatus, t, c, sd.group0, S, epoch, lane);
+  // a11 (first half): assemble the payload while the look-back reads are in flight
+  assemble_payload<T>(buf, cp, st.flags, S, lane);
+  wave_lds_sync();
+  // a10 (second half): exclusive prefix of the chunk sizes
+  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, smp);
+  copy_payload(buf, sd.out + kHdrBytes + 4 * nc + off, S, lane);
   if (lane == 0) reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = S;
   if (c == nc - 1) {
     write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
@@ -666,12 +697,23 @@ __device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, in
 // Chunk tickets of the compression kernel.  Chunks must be handed out in
 // stream order to waves that are running (the look-back waits only on
 // chunks whose owners already exist).  A single global counter serialises at
-// about 11 ns per atomic, so a workgroup takes batches of kWavesC
+// about 11 ns per atomic, so a workgroup takes batches of kTicketBatch
 // consecutive chunks with one global atomic and deals them to its waves
 // through an LDS slot counter: slot s of the workgroup is chunk
-// kWavesC * batch(s / kWavesC) + s % kWavesC.  The wave holding the first
-// slot of a round fetches the round's batch and posts it in a small LDS
-// ring; the others read it there.
+// kTicketBatch * batch(s / kTicketBatch) + s % kTicketBatch.  The wave
+// holding the first slot of a round fetches the round's batch and posts it
+// in an LDS ring of kTicketRing rounds; the others read it there.
+//
+// The batch is small because its chunks start only as the workgroup's waves
+// free up, one after another: the later a chunk of the batch starts, the
+// longer the chunks after it (claimed meanwhile by other workgroups) wait
+// for its size in the look-back.  Four chunks per atomic keep the counter
+// below a third of its serial rate at full speed.  A ring entry is reused
+// only kTicketRing * kTicketBatch = 64 slots later, far more claims than the
+// other waves can make while a waiter polls.
+constexpr uint32_t kTicketBatch = 4;
+constexpr uint32_t kTicketRing = 16;
+
 struct TicketClaim {
   uint32_t round, pos, batch;
 };
@@ -682,8 +724,8 @@ __device__ __forceinline__ TicketClaim claim_slot(BlockLdsT<NW>& sm, Ctl* ctl, i
   if (lane == 0) s = atomicAdd(&sm.slot_next, 1u);
   s = uniform(s);
   TicketClaim tc;
-  tc.round = s / NW;
-  tc.pos = s % NW;
+  tc.round = s / kTicketBatch;
+  tc.pos = s % kTicketBatch;
   tc.batch = 0;
   if (tc.pos == 0) {
     uint32_t b = 0;
@@ -696,7 +738,7 @@ __device__ __forceinline__ TicketClaim claim_slot(BlockLdsT<NW>& sm, Ctl* ctl, i
 template <int NW>
 __device__ __forceinline__ uint64_t resolve_slot(BlockLdsT<NW>& sm, TicketClaim tc, int lane) {
   uint32_t b;
-  const uint32_t ri = tc.round & 7u;
+  const uint32_t ri = tc.round % kTicketRing;
   if (tc.pos == 0) {
     b = uniform(tc.batch);
     if (lane == 0) {
@@ -709,7 +751,7 @@ __device__ __forceinline__ uint64_t resolve_slot(BlockLdsT<NW>& sm, TicketClaim 
     b = __hip_atomic_load(&sm.ring_batch[ri], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     b = uniform(b);
   }
-  return (uint64_t)b * NW + tc.pos;
+  return (uint64_t)b * kTicketBatch + tc.pos;
 }
 
 // Writes the 32-byte header of every empty series of a batch launch and its
@@ -747,7 +789,7 @@ template <int NW>
 __device__ __forceinline__ void compress_prologue(BlockLdsT<NW>& sm, const CompressArgs& a) {
   load_tables(sm.tab);
   if (threadIdx.x == 0) sm.slot_next = 0;
-  if (threadIdx.x < 8) sm.ring_round[threadIdx.x] = 0xFFFFFFFFu;
+  if (threadIdx.x < kTicketRing) sm.ring_round[threadIdx.x] = 0xFFFFFFFFu;
   empty_series_headers(a);
   __syncthreads();
 }
@@ -797,6 +839,114 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
   }
   exit_protocol(a.ctl, a.total_waves, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass compression.  The size pass runs a1-a9 for every chunk and keeps
+// what the write pass needs (ChunkMeta); the chunk sizes are then scanned
+// into offsets (k_scan_*), and the write pass reloads each chunk, redoes
+// a4-a7 with the case already decided, assembles the payload and writes it
+// at its offset.  No chunk ever waits for another, so waves take chunks by
+// static striding.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
+                                           const CompressSeries& sd, uint64_t t, int lane,
+                                           typename T::U (&vb)[17]) {
+  const uint64_t c = t - sd.chunk0;
+  load_chunk<T>(sd, c, lane, vb);
+  ChunkPlanes cp;
+  compress_front<T>(tab, buf, vb, lane, cp);
+  const ChunkStats st = chunk_stats<T>(cp);
+  if (lane == 0) {
+    ChunkMeta m;
+    m.flags = st.flags;
+    m.S = st.S;
+    m.A = (uint8_t)cp.A;
+    m.B = (uint8_t)cp.B;
+    m.w = (uint8_t)cp.w;
+    m.pad = 0;
+    a.meta[t] = m;
+    a.gsizes[t] = st.S;
+    reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = st.S;
+  }
+  wave_lds_sync();
+}
+
+template <class T>
+__device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
+                                            const CompressSeries& sd, uint64_t t, int lane,
+                                            typename T::U (&vb)[17]) {
+  const uint64_t c = t - sd.chunk0;
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  load_chunk<T>(sd, c, lane, vb);
+  const uint64_t* mp = reinterpret_cast<const uint64_t*>(a.meta + t);
+  const uint64_t flags = uniform64(mp[0]);
+  const uint64_t m1 = uniform64(mp[1]);
+  const uint32_t S = (uint32_t)m1;
+  ChunkPlanes cp;
+  cp.A = (int)((m1 >> 32) & 0xFF);
+  cp.B = (int)((m1 >> 40) & 0xFF);
+  compress_transform<T>(tab, buf, vb, lane, cp.A <= T::AMAX && cp.B <= T::BMAX, cp);
+  assemble_payload<T>(buf, cp, flags, S, lane);
+  const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(a.offsets[t]) - base;
+  wave_lds_sync();
+  copy_payload(buf, sd.out + kHdrBytes + 4 * nc + off, S, lane);
+  if (c == nc - 1) {
+    write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
+    if (a.lens && lane == 0) a.lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
+  }
+  wave_lds_sync();
+}
+
+template <int NW>
+__device__ __forceinline__ void pass_prologue(BlockLdsT<NW>& sm, const CompressArgs& a, bool headers) {
+  load_tables(sm.tab);
+  if (headers) empty_series_headers(a);
+  __syncthreads();
+}
+
+// PASS 1 = size pass, 2 = write pass; one dtype per launch.
+template <class T, int NW, int PASS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_pass(CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  pass_prologue(sm, a, PASS == 2);
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  uint8_t* buf = wave_bytes(sm, wid);
+  typename T::U vb[17];
+  if (PASS == 2 && a.total_chunks == 0 && !a.many && blockIdx.x == 0 && wid == 0)
+    write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
+  for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
+    const uint64_t tg = t + a.t0;
+    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    if (PASS == 1) size_chunk<T>(sm.tab, buf, a, sd, tg, lane, vb);
+    else write_chunk<T>(sm.tab, buf, a, sd, tg, lane, vb);
+  }
+}
+
+template <int NW, int PASS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_pass_mixed(
+    CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  pass_prologue(sm, a, PASS == 2);
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  uint8_t* buf = wave_bytes(sm, wid);
+  for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
+    const uint64_t tg = t + a.t0;
+    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    if (uniform(sd.dtype) == 2) {
+      uint64_t vb[17];
+      if (PASS == 1) size_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
+      else write_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
+    } else {
+      uint32_t vb[17];
+      if (PASS == 1) size_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
+      else write_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
+    }
+  }
 }
 
 // Decompression has no dependence between chunks once the offsets are

@@ -42,6 +42,10 @@ struct Lane {
   falcon_dev::Ctl* ctl = nullptr;
   uint8_t* stage = nullptr;     // pinned host bytes: [0,32) header, [32,36) error word, [40,48) payload size
   uint32_t epoch = 0;
+  falcon_dev::ChunkMeta* meta = nullptr;  // compression size pass results, one per chunk
+  size_t meta_cap = 0;
+  uint32_t* gsizes = nullptr;             // compression chunk sizes (scan input)
+  size_t gsizes_cap = 0;
 };
 
 falcon_status lane_init(Lane& l);
@@ -91,8 +95,10 @@ struct BatchScratch {
   size_t status_cap = 0;
   uint64_t* gstatus = nullptr;
   size_t gstatus_cap = 0;
-  uint32_t* sizes = nullptr;     // decompression: gathered chunk sizes
+  uint32_t* sizes = nullptr;     // decompression: gathered chunk sizes; compression: chunk sizes
   size_t sizes_cap = 0;
+  falcon_dev::ChunkMeta* meta = nullptr;  // compression size pass results
+  size_t meta_cap = 0;
   falcon_dev::Ctl* ctl = nullptr;
   uint64_t* lens = nullptr;      // device stream lengths (compression)
   size_t lens_cap = 0;
@@ -106,8 +112,9 @@ struct falcon_ctx {
   int device = 0;
   falcon_host::Lane main;
   // co-resident workgroups of each kernel: by form (1 = f32, 2 = f64,
-  // 3 = mixed) and, for compression, workgroup size (8 or 16 waves)
-  int grid_c[4][2] = {};
+  // 3 = mixed) and, for compression, pass (0 single-pass, 1 size, 2 write)
+  // and workgroup size (8 or 16 waves)
+  int grid_c[4][3][2] = {};
   int grid_d[4] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last timed kernel
   bool timed = false;
@@ -138,7 +145,7 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
                                  uint64_t payload, void* d_out, hipStream_t s, bool timed);
 inline bool decompress_failed(const Lane& l) { return rd32(l.stage + 32) == l.epoch; }
 
-inline int max_grid_c(const falcon_ctx* ctx, int form, int nw);
+inline int max_grid_c(const falcon_ctx* ctx, int form, int pass, int nw);
 inline int max_grid_d(const falcon_ctx* ctx, int form);
 
 // Frees the pipeline lanes and their buffers (pipeline.cpp).
@@ -161,5 +168,7 @@ void batch_free(BatchScratch& b);
 
 }  // namespace falcon_host
 
-inline int falcon_host::max_grid_c(const falcon_ctx* ctx, int form, int nw) { return ctx->grid_c[form][nw == 8 ? 0 : 1]; }
+inline int falcon_host::max_grid_c(const falcon_ctx* ctx, int form, int pass, int nw) {
+  return ctx->grid_c[form][pass][nw == 8 ? 0 : 1];
+}
 inline int falcon_host::max_grid_d(const falcon_ctx* ctx, int form) { return ctx->grid_d[form]; }

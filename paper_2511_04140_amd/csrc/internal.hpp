@@ -42,6 +42,15 @@ struct DecompressSeries {
   uint32_t idx;
 };
 
+// What the size pass of compression learns about a chunk and the write pass
+// reuses: the row scheme flags (bit p set = plane p is written dense), the
+// chunk's byte count, and its header bytes alpha_max, beta_hat_max, w.
+struct ChunkMeta {
+  uint64_t flags;
+  uint32_t S;
+  uint8_t A, B, w, pad;
+};
+
 struct CompressArgs {
   CompressSeries one;            // used when nseries == 1
   const CompressSeries* many;    // device array, sorted by chunk0, when nseries > 1
@@ -53,8 +62,11 @@ struct CompressArgs {
   uint64_t* gstatus;   // one word per 64-chunk group of each series
   Ctl* ctl;
   uint64_t* lens;      // batch launches: stream length of each series (device), else null
+  ChunkMeta* meta;     // two-pass compression: one per launch chunk
+  uint32_t* gsizes;    // two-pass compression: chunk sizes by launch chunk (scan input)
+  const uint64_t* offsets;  // two-pass compression: exclusive prefix of gsizes
   uint32_t epoch;
-  uint32_t pad;
+  uint32_t relative;   // 1: offsets run over all series; a series subtracts its first one
 };
 
 struct DecompressArgs {
@@ -77,18 +89,23 @@ constexpr int kDecompressWaves = 4;   // wavefronts per decompression workgroup
 // one (3) that takes either dtype per series.  nw = wavefronts per
 // compression workgroup, 8 or 16.
 constexpr int kFormMixed = 3;
-hipError_t launch_compress(const CompressArgs& a, int form, int nw, int grid, hipStream_t s);
+// pass 0: the single-pass kernel (decoupled look-back, chunk tickets);
+// pass 1: the size pass of two-pass compression (meta, gsizes and the
+// series' size arrays); pass 2: its write pass, after a scan of gsizes into
+// offsets.
+hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s);
 // per-form entry points (one translation unit each)
-hipError_t launch_compress_f64(const CompressArgs& a, int nw, int grid, hipStream_t s);
-hipError_t launch_compress_f32(const CompressArgs& a, int nw, int grid, hipStream_t s);
-hipError_t launch_compress_mixed(const CompressArgs& a, int nw, int grid, hipStream_t s);
+// pass: 0 = single-pass look-back kernel, 1 = size pass, 2 = write pass
+hipError_t launch_compress_f64(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_f32(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_mixed(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_decompress_f64(const DecompressArgs& a, int grid, hipStream_t s);
 hipError_t launch_decompress_f32(const DecompressArgs& a, int grid, hipStream_t s);
 hipError_t launch_decompress_mixed(const DecompressArgs& a, int grid, hipStream_t s);
-const void* compress_kernel_f64(int nw);
-const void* compress_kernel_f32(int nw);
-const void* compress_kernel_mixed(int nw);
+const void* compress_kernel_f64(int pass, int nw);
+const void* compress_kernel_f32(int pass, int nw);
+const void* compress_kernel_mixed(int pass, int nw);
 const void* decompress_kernel_f64();
 const void* decompress_kernel_f32();
 const void* decompress_kernel_mixed();
@@ -107,7 +124,7 @@ uint64_t scan_tiles(uint64_t n);
 hipError_t launch_batch_dprep(DecompressSeries* many, uint32_t ns, uint64_t total_chunks, uint32_t* sizes_out,
                               Ctl* ctl, uint32_t epoch, hipStream_t s);
 // Largest number of co-resident workgroups of each kernel on the device.
-int max_grid_compress(int device, int form, int nw);
+int max_grid_compress(int device, int form, int pass, int nw);
 int max_grid_decompress(int device, int form);
 
 }  // namespace falcon_dev

@@ -143,10 +143,10 @@ hipError_t launch_batch_dprep(DecompressSeries* many, uint32_t ns, uint64_t tota
   return hipGetLastError();
 }
 
-hipError_t launch_compress(const CompressArgs& a, int form, int nw, int grid, hipStream_t s) {
-  if (form == 2) return launch_compress_f64(a, nw, grid, s);
-  if (form == 1) return launch_compress_f32(a, nw, grid, s);
-  return launch_compress_mixed(a, nw, grid, s);
+hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, int grid, hipStream_t s) {
+  if (form == 2) return launch_compress_f64(a, pass, nw, grid, s);
+  if (form == 1) return launch_compress_f32(a, pass, nw, grid, s);
+  return launch_compress_mixed(a, pass, nw, grid, s);
 }
 
 hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s) {
@@ -183,9 +183,9 @@ static int max_grid_of(const void* fn, int device, int block) {
   return per_cu * prop.multiProcessorCount;
 }
 
-int max_grid_compress(int device, int form, int nw) {
-  const void* fn = form == 2 ? compress_kernel_f64(nw) : form == 1 ? compress_kernel_f32(nw)
-                                                                    : compress_kernel_mixed(nw);
+int max_grid_compress(int device, int form, int pass, int nw) {
+  const void* fn = form == 2 ? compress_kernel_f64(pass, nw)
+                             : form == 1 ? compress_kernel_f32(pass, nw) : compress_kernel_mixed(pass, nw);
   return max_grid_of(fn, device, 64 * nw);
 }
 

@@ -4,10 +4,16 @@
 
 namespace falcon_dev {
 
-hipError_t launch_compress_f64(const CompressArgs& a, int nw, int grid, hipStream_t s) {
-  if (nw == 8) hipLaunchKernelGGL((k_compress<TF64, 8>), dim3(grid), dim3(64 * 8), 0, s, a);
-  else hipLaunchKernelGGL((k_compress<TF64, 16>), dim3(grid), dim3(64 * 16), 0, s, a);
+template <int NW>
+static hipError_t launch_nw(const CompressArgs& a, int pass, int grid, hipStream_t s) {
+  if (pass == 1) hipLaunchKernelGGL((k_compress_pass<TF64, NW, 1>), dim3(grid), dim3(64 * NW), 0, s, a);
+  else if (pass == 2) hipLaunchKernelGGL((k_compress_pass<TF64, NW, 2>), dim3(grid), dim3(64 * NW), 0, s, a);
+  else hipLaunchKernelGGL((k_compress<TF64, NW>), dim3(grid), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_compress_f64(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s) {
+  return nw == 8 ? launch_nw<8>(a, pass, grid, s) : launch_nw<16>(a, pass, grid, s);
 }
 
 hipError_t launch_decompress_f64(const DecompressArgs& a, int grid, hipStream_t s) {
@@ -15,10 +21,14 @@ hipError_t launch_decompress_f64(const DecompressArgs& a, int grid, hipStream_t 
   return hipGetLastError();
 }
 
-const void* compress_kernel_f64(int nw) {
-  return nw == 8 ? reinterpret_cast<const void*>(&k_compress<TF64, 8>)
-                 : reinterpret_cast<const void*>(&k_compress<TF64, 16>);
+template <int NW>
+static const void* kernel_nw(int pass) {
+  if (pass == 1) return reinterpret_cast<const void*>(&k_compress_pass<TF64, NW, 1>);
+  if (pass == 2) return reinterpret_cast<const void*>(&k_compress_pass<TF64, NW, 2>);
+  return reinterpret_cast<const void*>(&k_compress<TF64, NW>);
 }
+
+const void* compress_kernel_f64(int pass, int nw) { return nw == 8 ? kernel_nw<8>(pass) : kernel_nw<16>(pass); }
 
 const void* decompress_kernel_f64() { return reinterpret_cast<const void*>(&k_decompress<TF64>); }
 
