@@ -2,11 +2,9 @@
 // context life cycle and the device-resident compress / decompress calls.
 //
 // A context owns a main lane (a HIP stream, a small pinned staging buffer
-// for the few bytes read back per call, the per-chunk status words of the
-// decoupled look-back and the launch control block) and, once the host
-// pipeline is used, one lane per pipeline stream.  Status words carry a
-// 16-bit launch epoch, so they are cleared only when the array grows or the
-// epoch wraps.
+// for the few bytes read back per call, the chunk offsets and size-pass
+// results of its launches, and the control block) and, once the host
+// pipeline is used, one lane per pipeline stream.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -43,8 +41,8 @@ falcon_status lane_init(Lane& l) {
 
 void lane_free(Lane& l) {
   if (l.stream) (void)hipStreamSynchronize(l.stream);
-  if (l.status) (void)hipFree(l.status);
-  if (l.gstatus) (void)hipFree(l.gstatus);
+  if (l.offsets) (void)hipFree(l.offsets);
+  if (l.tiles) (void)hipFree(l.tiles);
   if (l.meta) (void)hipFree(l.meta);
   if (l.gsizes) (void)hipFree(l.gsizes);
   if (l.ctl) (void)hipFree(l.ctl);
@@ -72,34 +70,15 @@ falcon_status grow_raw(P** arr, size_t* cap, uint64_t n, hipStream_t s) {
   return FALCON_OK;
 }
 
-// Grows a zeroed status array to at least n words.
-falcon_status grow_zeroed(uint64_t** arr, size_t* cap, uint64_t n, hipStream_t s) {
-  if (n <= *cap) return FALCON_OK;
-  size_t c = *cap ? *cap : 1024;
-  while (c < n) c *= 2;
-  // the stream may still use the old array: wait before freeing it
-  if (hipStreamSynchronize(s) != hipSuccess) return FALCON_ERR_DEVICE;
-  if (*arr) (void)hipFree(*arr);
-  *arr = nullptr;
-  *cap = 0;
-  if (hipMalloc(arr, c * sizeof(uint64_t)) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
-  *cap = c;
-  return launch_fill_u64(*arr, c, 0, s) == hipSuccess ? FALCON_OK : FALCON_ERR_DEVICE;
-}
-
-// Makes the lane's status arrays hold nchunks chunk words and ngroups group
-// words, and advances the launch epoch.
-falcon_status prepare_launch(Lane& l, uint64_t nchunks, uint64_t ngroups, hipStream_t s) {
-  falcon_status st = grow_zeroed(&l.status, &l.status_cap, nchunks, s);
-  if (st == FALCON_OK) st = grow_zeroed(&l.gstatus, &l.gstatus_cap, ngroups, s);
+// Makes the lane's arrays hold nchunks chunk offsets and ntiles scan tile
+// sums, and advances the launch epoch (the value a failing decompression
+// launch leaves in the error word).
+falcon_status prepare_launch(Lane& l, uint64_t nchunks, uint64_t ntiles, hipStream_t s) {
+  falcon_status st = grow_raw(&l.offsets, &l.offsets_cap, nchunks, s);
+  if (st == FALCON_OK) st = grow_raw(&l.tiles, &l.tiles_cap, ntiles, s);
   if (st != FALCON_OK) return st;
   l.epoch += 1;
-  if ((l.epoch & 0xFFFF) == 0) {  // epoch tag wrapped: clear old words
-    l.epoch += 1;
-    if (launch_fill_u64(l.status, l.status_cap, 0, s) != hipSuccess ||
-        launch_fill_u64(l.gstatus, l.gstatus_cap, 0, s) != hipSuccess)
-      return FALCON_ERR_DEVICE;
-  }
+  if (l.epoch == 0) l.epoch = 1;
   return FALCON_OK;
 }
 
@@ -112,7 +91,7 @@ int grid_for(int max_grid, uint64_t nchunks, int waves_per_block) {
 }  // namespace
 
 // Two-pass compression: size pass, scan of the sizes, write pass (see
-// codec_kernels.hpp).  The lane's status array receives the offsets.
+// codec_kernels.hpp).  The lane's offset array receives the scan.
 falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
                                hipStream_t s, bool timed) {
   const uint64_t nc = chunks_of(n);
@@ -125,19 +104,14 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.one.out = static_cast<uint8_t*>(d_out);
   a.one.n = n;
   a.one.chunk0 = 0;
-  a.one.group0 = 0;
   a.one.dtype = (uint32_t)dt;
   a.many = nullptr;
   a.nseries = 1;
   a.total_chunks = nc;
-  a.status = l.status;
-  a.gstatus = l.gstatus;
-  a.ctl = l.ctl;
   a.lens = nullptr;
   a.meta = l.meta;
   a.gsizes = l.gsizes;
-  a.offsets = l.status;
-  a.epoch = l.epoch;
+  a.offsets = l.offsets;
   a.relative = 0;
   const int g1 = grid_for(max_grid_c(ctx, dt, 1, kCompressWaves), nc, kCompressWaves);
   const int g2 = grid_for(max_grid_c(ctx, dt, 2, kCompressWaves), nc, kCompressWaves);
@@ -148,7 +122,7 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   if (nc) {
     a.total_waves = (uint32_t)(g1 * kCompressWaves);
     if ((st = dev_err(launch_compress(a, (int)dt, 1, kCompressWaves, g1, s))) != FALCON_OK) return st;
-    if ((st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.gstatus, l.status, l.ctl, l.epoch, s))) !=
+    if ((st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch, s))) !=
         FALCON_OK)
       return st;
   }
@@ -164,29 +138,27 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
 falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t n, falcon_dtype dt,
                                  uint64_t payload, void* d_out, hipStream_t s, bool timed) {
   const uint64_t nc = chunks_of(n);
-  falcon_status st = prepare_launch(l, nc, groups_of(nc) + scan_tiles(nc) + 1, s);
+  falcon_status st = prepare_launch(l, nc, scan_tiles(nc) + 1, s);
   if (st != FALCON_OK) return st;
-  // chunk offsets: exclusive prefix of the size array, written into the
-  // status array (offsets carry a zero epoch tag, so a later compression
-  // never mistakes them for look-back words); the tile sums go to gstatus.
+  // chunk offsets: exclusive prefix of the size array (which the scan also
+  // checks: every size in [lo, hi], their sum equal to the payload bytes).
   const uint32_t lo = dt == FALCON_FLOAT64 ? 11u : 7u;
   const uint32_t hi = (uint32_t)max_chunk_bytes(dt);
   if (timed) ctx->timed = false;
-  if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi, payload, l.gstatus,
-                                      l.status, l.ctl, l.epoch, s))) != FALCON_OK)
+  if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi, payload, l.tiles,
+                                      l.offsets, l.ctl, l.epoch, s))) != FALCON_OK)
     return st;
   DecompressArgs a{};
   a.one.in = d_in;
   a.one.out = static_cast<uint8_t*>(d_out);
   a.one.n = n;
   a.one.chunk0 = 0;
-  a.one.group0 = 0;
   a.one.payload_bytes = payload;
   a.one.dtype = (uint32_t)dt;
   a.many = nullptr;
   a.nseries = 1;
   a.total_chunks = nc;
-  a.status = l.status;
+  a.offsets = l.offsets;
   a.ctl = l.ctl;
   a.epoch = l.epoch;
   a.relative = 0;
@@ -240,7 +212,7 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
     return FALCON_ERR_DEVICE;
   }
   for (int form = 1; form <= 3; ++form) {
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 1; pass <= 2; ++pass) {
       ctx->grid_c[form][pass][0] = max_grid_compress(device, form, pass, 8);
       ctx->grid_c[form][pass][1] = max_grid_compress(device, form, pass, 16);
     }

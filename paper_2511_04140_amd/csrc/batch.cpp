@@ -95,7 +95,7 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
   L.desc_bytes = count * dsz;
   falcon_status r = grow(&b.h_desc, &b.h_desc_cap, L.desc_bytes, 1, true, st);
   if (r != FALCON_OK) return r;
-  uint64_t t = 0, g = 0;
+  uint64_t t = 0;
   size_t k = 0;
   for (int pass = 0; pass < 2; ++pass) {  // float64 series first, then float32
     for (size_t i = 0; i < count; ++i) {
@@ -108,7 +108,6 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
         c.out = static_cast<uint8_t*>(d.d_out);
         c.n = d.n;
         c.chunk0 = t;
-        c.group0 = g;
         c.dtype = (uint32_t)d.dtype;
         c.idx = (uint32_t)i;
         memcpy(b.h_desc + k * dsz, &c, dsz);
@@ -119,7 +118,6 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
         c.out = static_cast<uint8_t*>(d.d_out);
         c.n = d.n;
         c.chunk0 = t;
-        c.group0 = g;
         c.in_len = d.in_len;
         c.dtype = (uint32_t)d.dtype;
         c.idx = (uint32_t)i;
@@ -134,15 +132,13 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
         L.has32 |= nc > 0;
       }
       t += nc;
-      g += groups_of(nc);
     }
   }
   L.total = t;
-  L.groups = g;
   const size_t gwords = scan_tiles(t) + 1;
   if ((r = grow(&b.many, &b.many_cap, L.desc_bytes, 1, false, st)) != FALCON_OK ||
-      (r = grow(&b.status, &b.status_cap, t ? t : 1, 8, false, st)) != FALCON_OK ||
-      (r = grow(&b.gstatus, &b.gstatus_cap, gwords, 8, false, st)) != FALCON_OK ||
+      (r = grow(&b.offsets, &b.offsets_cap, t ? t : 1, 8, false, st)) != FALCON_OK ||
+      (r = grow(&b.tiles, &b.tiles_cap, gwords, 8, false, st)) != FALCON_OK ||
       (r = grow(&b.lens, &b.lens_cap, count, 8, false, st)) != FALCON_OK ||
       (r = grow(&b.h_lens, &b.h_lens_cap, count + 1, 8, true, st)) != FALCON_OK)
     return r;
@@ -179,14 +175,10 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     a.one = L.one_c;
     a.many = static_cast<const CompressSeries*>(b.many);
     a.nseries = (uint32_t)L.count;
-    a.status = b.status;
-    a.gstatus = b.gstatus;
-    a.ctl = b.ctl;
     a.lens = b.lens;
     a.meta = b.meta;
     a.gsizes = b.sizes;
-    a.offsets = b.status;
-    a.epoch = kBatchEpoch;
+    a.offsets = b.offsets;
     a.relative = 1;
     for (int pass = 1; pass <= 2; ++pass) {
       for (int i = 0; i < np; ++i) {
@@ -198,7 +190,7 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
         if ((st = dev_err(launch_compress(a, parts[i].form, pass, g.nw, grid, s))) != FALCON_OK) return st;
       }
       if (pass == 1 && L.total &&
-          (st = dev_err(launch_scan_sizes(b.sizes, L.total, 0, ~0u, ~0ull, b.gstatus, b.status, b.ctl, kBatchEpoch,
+          (st = dev_err(launch_scan_sizes(b.sizes, L.total, 0, ~0u, ~0ull, b.tiles, b.offsets, b.ctl, kBatchEpoch,
                                           s))) != FALCON_OK)
         return st;
     }
@@ -210,7 +202,7 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
   DecompressSeries* many = static_cast<DecompressSeries*>(b.many);
   if ((st = dev_err(launch_batch_dprep(many, (uint32_t)L.count, L.total, b.sizes, b.ctl, kBatchEpoch, s))) !=
           FALCON_OK ||
-      (st = dev_err(launch_scan_sizes(b.sizes, L.total, 7, (uint32_t)kF64Chunk, ~0ull, b.gstatus, b.status, b.ctl,
+      (st = dev_err(launch_scan_sizes(b.sizes, L.total, 7, (uint32_t)kF64Chunk, ~0ull, b.tiles, b.offsets, b.ctl,
                                       kBatchEpoch, s))) != FALCON_OK)
     return st;
   for (int i = 0; i < np; ++i) {
@@ -220,7 +212,7 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     a.nseries = (uint32_t)L.count;
     a.total_chunks = parts[i].chunks;
     a.t0 = parts[i].t0;
-    a.status = b.status;
+    a.offsets = b.offsets;
     a.ctl = b.ctl;
     a.epoch = kBatchEpoch;
     a.relative = 1;
@@ -246,8 +238,8 @@ falcon_status batch_result(const BatchScratch& b, const BatchLayout& L, const fa
 void batch_free(BatchScratch& b) {
   if (b.many) (void)hipFree(b.many);
   if (b.h_desc) (void)hipHostFree(b.h_desc);
-  if (b.status) (void)hipFree(b.status);
-  if (b.gstatus) (void)hipFree(b.gstatus);
+  if (b.offsets) (void)hipFree(b.offsets);
+  if (b.tiles) (void)hipFree(b.tiles);
   if (b.sizes) (void)hipFree(b.sizes);
   if (b.meta) (void)hipFree(b.meta);
   if (b.ctl) (void)hipFree(b.ctl);

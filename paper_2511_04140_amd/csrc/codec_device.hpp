@@ -56,8 +56,7 @@ __constant__ float c_pow10_f32[21] = {
     0x1.2a05f2p+33f};
 
 // Shared memory of one workgroup: the power tables (copied once per block so
-// that per-lane lookups are LDS reads), the chunk-ticket ring of the
-// compression kernel, and one byte buffer per wavefront.
+// that per-lane lookups are LDS reads) and one byte buffer per wavefront.
 struct __attribute__((aligned(16))) LdsTables {
   double p64[48];
   float p32[24];
@@ -65,10 +64,6 @@ struct __attribute__((aligned(16))) LdsTables {
 template <int NW>
 struct __attribute__((aligned(16))) BlockLdsT {
   LdsTables tab;
-  uint32_t slot_next;      // next ticket slot of this workgroup
-  uint32_t ring_round[16]; // round whose batch index sits in ring_batch
-  uint32_t ring_batch[16];
-  uint32_t pad[3];
   uint4 wave[NW][kWaveLds / 16];
 };
 
@@ -248,128 +243,6 @@ __device__ __forceinline__ void xpose16(uint32_t (&a)[16]) {
       a[i] = (x & ~ms) | ((y << s) & ms);
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// Two-level decoupled look-back (Sec. 3.4: the compressed chunk sizes are
-// synchronised into offsets with a decoupled look-back).
-//
-// Status words, one per chunk and one per group of 64 consecutive chunks of
-// a series: bits 63..48 launch epoch, 47..46 flag (1 = aggregate: the
-// chunk's or group's own byte count; 2 = inclusive prefix), 45..0 value.
-// The epoch lets successive launches reuse the arrays without clearing them.
-//
-// A chunk publishes its aggregate, then reads the status of the chunks
-// before it in its group (one window of at most 63 lanes).  If one of them
-// already holds an inclusive prefix the answer follows directly.  Otherwise
-// the chunk needs the exclusive prefix of its group, which it finds by a
-// look-back over the group words (64 groups per window): the last chunk of
-// each group publishes the group aggregate as soon as it has summed its
-// window, and the group's inclusive prefix once it knows its own offset.
-// The depth of the walk is thus the number of groups in flight, not the
-// number of chunks in flight.
-// ---------------------------------------------------------------------------
-constexpr uint64_t kValMask = (1ull << 46) - 1;
-constexpr uint32_t kFlagAgg = 1, kFlagPrefix = 2;
-
-__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, uint64_t v) {
-  return ((uint64_t)(epoch & 0xFFFF) << 48) | ((uint64_t)flag << 46) | (v & kValMask);
-}
-
-// Window evaluation: lanes hold status words of consecutive predecessors,
-// nearest first (lane 0).  Returns false if a word needed for the answer is
-// not ready yet.  Otherwise sum = value of the nearest prefix word plus the
-// aggregates before it (or of all lanes if none is a prefix), found = whether
-// a prefix word was met.
-__device__ __forceinline__ bool window_sum(uint64_t s, bool valid, uint32_t epoch, uint64_t& sum, bool& found) {
-  const bool mine = (s >> 48) == (uint64_t)(epoch & 0xFFFF);
-  const uint32_t flag = (uint32_t)(s >> 46) & 3u;
-  const bool ready = !valid || (mine && flag != 0);
-  const bool isp = valid && mine && flag == kFlagPrefix;
-  const uint64_t pm = ballot(isp), nm = ballot(!ready);
-  const int firstp = pm ? (int)__builtin_ctzll(pm) : 64;
-  const uint64_t win = firstp >= 63 ? ~0ull : ((2ull << firstp) - 1);
-  if (nm & win) return false;
-  const int lane = lane_id();
-  sum = uniform64(wave_sum64((valid && lane <= firstp) ? (s & kValMask) : 0));
-  found = firstp < 64;
-  return true;
-}
-
-struct LookbackSamples {
-  uint64_t intra;  // status of chunk t-1-lane (lanes below the in-group position)
-  uint64_t group;  // status of group g-1-lane
-};
-
-// Publishes the chunk aggregate and issues the loads of both windows (the
-// chunks before it in its group, and the 64 groups before its group), so
-// that their latencies overlap with each other and with the caller's work.
-// c is the chunk's index in its series, t its status index, gbase the index
-// of the series' first group word.
-__device__ __forceinline__ LookbackSamples lookback_begin(uint64_t* status, uint64_t* gstatus, uint64_t t,
-                                                          uint64_t c, uint64_t gbase, uint64_t agg,
-                                                          uint32_t epoch, int lane) {
-  const uint32_t j = (uint32_t)(c & 63);
-  const int64_t g = (int64_t)(c >> 6);
-  if (lane == 0) status_store(status + t, status_word(epoch, c == 0 ? kFlagPrefix : kFlagAgg, agg));
-  LookbackSamples smp;
-  smp.intra = (lane < (int)j) ? status_load(status + t - 1 - lane) : 0;
-  smp.group = (g - 1 - lane >= 0) ? status_load(gstatus + gbase + (g - 1 - lane)) : 0;
-  return smp;
-}
-
-// Completes the look-back; returns the chunk's exclusive prefix.
-__device__ __forceinline__ uint64_t lookback_end(uint64_t* status, uint64_t* gstatus, uint64_t t, uint64_t c,
-                                                 uint64_t gbase, uint64_t agg, uint32_t epoch, int lane,
-                                                 LookbackSamples smp) {
-  if (c == 0) return 0;  // the prefix word was published by lookback_begin
-  const uint32_t j = (uint32_t)(c & 63);
-  const uint64_t g = c >> 6;
-  uint64_t intra = 0;
-  bool found = false;
-  if (j > 0) {
-    const bool valid = lane < (int)j;
-    uint64_t sample = smp.intra;
-    while (!window_sum(sample, valid, epoch, intra, found)) {
-      __builtin_amdgcn_s_sleep(1);
-      sample = valid ? status_load(status + t - 1 - lane) : 0;
-    }
-  }
-  uint64_t excl;
-  if (found) {
-    excl = intra;
-  } else {
-    if (j == 63 && lane == 0) status_store(gstatus + gbase + g, status_word(epoch, kFlagAgg, intra + agg));
-    uint64_t gx = 0;
-    int64_t k = (int64_t)g - 1;  // nearest group first
-    uint64_t s = smp.group;
-    while (k >= 0) {
-      const int64_t idx = k - lane;
-      const bool valid = idx >= 0;
-      uint64_t part;
-      bool gfound;
-      while (!window_sum(s, valid, epoch, part, gfound)) {
-        __builtin_amdgcn_s_sleep(1);
-        s = valid ? status_load(gstatus + gbase + idx) : 0;
-      }
-      gx += part;
-      if (gfound) break;
-      k -= 64;
-      s = (k - lane >= 0) ? status_load(gstatus + gbase + (k - lane)) : 0;
-    }
-    excl = gx + intra;
-  }
-  if (lane == 0) {
-    status_store(status + t, status_word(epoch, kFlagPrefix, excl + agg));
-    if (j == 63) status_store(gstatus + gbase + g, status_word(epoch, kFlagPrefix, excl + agg));
-  }
-  return excl;
 }
 
 // Byte access into a wave's LDS buffer.

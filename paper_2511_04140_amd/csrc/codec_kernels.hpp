@@ -1,12 +1,9 @@
 // codec_kernels.hpp -- Falcon compression and decompression kernels for
 // gfx950 (device code; each kernels_*.hip instantiates one form).
 //
-// Both kernels are persistent: each wavefront repeatedly takes a ticket (the
-// next chunk in stream order) from a device counter, processes the chunk,
-// and exits once the tickets run out.  Tickets make the chunk order match
-// the order in which waves start, which the decoupled look-back needs for
-// forward progress (a chunk only waits for chunks whose owners are already
-// running).
+// Compression runs in two passes (size pass, scan of the sizes, write
+// pass) and decompression after a scan of the size array, so no chunk ever
+// waits for another: waves take chunks by static striding.
 #pragma once
 
 #include <type_traits>
@@ -480,32 +477,6 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dst, u
   }
 }
 
-// a8-a11 in one pass: row schemes and sizes, look-back, payload assembly
-// and write-out.
-template <class T>
-__device__ __forceinline__ void compress_back(uint8_t* buf, const CompressSeries& sd, uint64_t c, uint64_t nc,
-                                              uint64_t t, uint64_t* status, uint64_t* gstatus, uint32_t epoch,
-                                              uint64_t* lens, int lane_in, const ChunkPlanes& cp) {
-  int lane = lane_in;  // opaque, see compress_transform
-  asm volatile("" : "+v"(lane));
-  const ChunkStats st = chunk_stats<T>(cp);
-  const uint32_t S = st.S;
-  // a10 (first half): publish the chunk size and issue the look-back reads
-  const LookbackSamples smp = lookback_begin(status, gstatus, t, c, sd.group0, S, epoch, lane);
-  // a11 (first half): assemble the payload while the look-back reads are in flight
-  assemble_payload<T>(buf, cp, st.flags, S, lane);
-  wave_lds_sync();
-  // a10 (second half): exclusive prefix of the chunk sizes
-  const uint64_t off = lookback_end(status, gstatus, t, c, sd.group0, S, epoch, lane, smp);
-  copy_payload(buf, sd.out + kHdrBytes + 4 * nc + off, S, lane);
-  if (lane == 0) reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = S;
-  if (c == nc - 1) {
-    write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
-    if (lens && lane == 0) lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
-  }
-  wave_lds_sync();
-}
-
 // ---------------------------------------------------------------------------
 // Decompression of one chunk (Sec. 4, executed by one wave)
 // ---------------------------------------------------------------------------
@@ -670,7 +641,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
 }
 
 // ---------------------------------------------------------------------------
-// Kernels (one instantiation per dtype; a launch carries series of one dtype)
+// Kernels
 // ---------------------------------------------------------------------------
 template <class Series>
 __device__ __forceinline__ Series find_series(const Series& one, const Series* many, uint32_t ns, uint64_t t) {
@@ -682,76 +653,6 @@ __device__ __forceinline__ Series find_series(const Series& one, const Series* m
     else hi = mid - 1;
   }
   return many[lo];
-}
-
-__device__ __forceinline__ void exit_protocol(Ctl* ctl, uint32_t total_waves, int lane) {
-  if (lane == 0) {
-    const uint32_t e = atomicAdd(&ctl->exited, 1u);
-    if (e + 1 == total_waves) {
-      __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
-// Chunk tickets of the compression kernel.  Chunks must be handed out in
-// stream order to waves that are running (the look-back waits only on
-// chunks whose owners already exist).  A single global counter serialises at
-// about 11 ns per atomic, so a workgroup takes batches of kTicketBatch
-// consecutive chunks with one global atomic and deals them to its waves
-// through an LDS slot counter: slot s of the workgroup is chunk
-// kTicketBatch * batch(s / kTicketBatch) + s % kTicketBatch.  The wave
-// holding the first slot of a round fetches the round's batch and posts it
-// in an LDS ring of kTicketRing rounds; the others read it there.
-//
-// The batch is small because its chunks start only as the workgroup's waves
-// free up, one after another: the later a chunk of the batch starts, the
-// longer the chunks after it (claimed meanwhile by other workgroups) wait
-// for its size in the look-back.  Four chunks per atomic keep the counter
-// below a third of its serial rate at full speed.  A ring entry is reused
-// only kTicketRing * kTicketBatch = 64 slots later, far more claims than the
-// other waves can make while a waiter polls.
-constexpr uint32_t kTicketBatch = 4;
-constexpr uint32_t kTicketRing = 16;
-
-struct TicketClaim {
-  uint32_t round, pos, batch;
-};
-
-template <int NW>
-__device__ __forceinline__ TicketClaim claim_slot(BlockLdsT<NW>& sm, Ctl* ctl, int lane) {
-  uint32_t s = 0;
-  if (lane == 0) s = atomicAdd(&sm.slot_next, 1u);
-  s = uniform(s);
-  TicketClaim tc;
-  tc.round = s / kTicketBatch;
-  tc.pos = s % kTicketBatch;
-  tc.batch = 0;
-  if (tc.pos == 0) {
-    uint32_t b = 0;
-    if (lane == 0) b = atomicAdd(&ctl->ticket, 1u);
-    tc.batch = b;  // resolved (made uniform and posted) in resolve_slot
-  }
-  return tc;
-}
-
-template <int NW>
-__device__ __forceinline__ uint64_t resolve_slot(BlockLdsT<NW>& sm, TicketClaim tc, int lane) {
-  uint32_t b;
-  const uint32_t ri = tc.round % kTicketRing;
-  if (tc.pos == 0) {
-    b = uniform(tc.batch);
-    if (lane == 0) {
-      __hip_atomic_store(&sm.ring_batch[ri], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_store(&sm.ring_round[ri], tc.round, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  } else {
-    while (__hip_atomic_load(&sm.ring_round[ri], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != tc.round)
-      __builtin_amdgcn_s_sleep(1);
-    b = __hip_atomic_load(&sm.ring_batch[ri], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    b = uniform(b);
-  }
-  return (uint64_t)b * kTicketBatch + tc.pos;
 }
 
 // Writes the 32-byte header of every empty series of a batch launch and its
@@ -770,75 +671,6 @@ __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
     o[3] = o[4] = o[5] = o[6] = o[7] = 0;
     if (a.lens) a.lens[sd.idx] = kHdrBytes;
   }
-}
-
-// One chunk of compression, a1-a11, by one wave.
-template <class T>
-__device__ __forceinline__ void compress_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
-                                               const CompressSeries& sd, uint64_t t, int lane,
-                                               typename T::U (&vb)[17]) {
-  const uint64_t c = t - sd.chunk0;
-  load_chunk<T>(sd, c, lane, vb);
-  ChunkPlanes cp;
-  compress_front<T>(tab, buf, vb, lane, cp);
-  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-  compress_back<T>(buf, sd, c, nc, t, a.status, a.gstatus, a.epoch, a.lens, lane, cp);
-}
-
-template <int NW>
-__device__ __forceinline__ void compress_prologue(BlockLdsT<NW>& sm, const CompressArgs& a) {
-  load_tables(sm.tab);
-  if (threadIdx.x == 0) sm.slot_next = 0;
-  if (threadIdx.x < kTicketRing) sm.ring_round[threadIdx.x] = 0xFFFFFFFFu;
-  empty_series_headers(a);
-  __syncthreads();
-}
-
-// One dtype per launch.  A chunk is claimed only when the wave is ready to
-// work on it: a claimed chunk that waited behind another chunk's look-back
-// would delay its own size, and with it the look-back of every chunk after
-// it.
-template <class T, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress(CompressArgs a) {
-  __shared__ BlockLdsT<NW> sm;
-  compress_prologue(sm, a);
-  const int lane = lane_id();
-  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  typename T::U vb[17];
-  for (;;) {
-    const uint64_t t = resolve_slot(sm, claim_slot(sm, a.ctl, lane), lane);
-    if (t >= a.total_chunks) {
-      if (t == 0 && a.nseries == 1) write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
-      break;
-    }
-    const uint64_t tg = t + a.t0;
-    compress_chunk<T>(sm.tab, buf, a, find_series(a.one, a.many, a.nseries, tg), tg, lane, vb);
-  }
-  exit_protocol(a.ctl, a.total_waves, lane);
-}
-
-// Series of both dtypes in one launch: the wave branches on the dtype of
-// the chunk's series (uniform across the wave).
-template <int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_mixed(CompressArgs a) {
-  __shared__ BlockLdsT<NW> sm;
-  compress_prologue(sm, a);
-  const int lane = lane_id();
-  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  for (;;) {
-    const uint64_t t = resolve_slot(sm, claim_slot(sm, a.ctl, lane), lane);
-    if (t >= a.total_chunks) break;
-    const uint64_t tg = t + a.t0;
-    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
-    if (uniform(sd.dtype) == 2) {
-      uint64_t vb[17];
-      compress_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
-    } else {
-      uint32_t vb[17];
-      compress_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
-    }
-  }
-  exit_protocol(a.ctl, a.total_waves, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -956,8 +788,8 @@ __device__ __forceinline__ void decompress_one(const LdsTables& tab, uint8_t* bu
                                                const DecompressSeries& sd, uint64_t t, int lane) {
   const uint64_t c = t - sd.chunk0;
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-  const uint64_t base = a.relative ? uniform64(a.status[sd.chunk0]) : 0;
-  decompress_chunk<T>(tab, buf, sd, c, nc, t, a.status, base, a.epoch, lane, a.ctl);
+  const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
+  decompress_chunk<T>(tab, buf, sd, c, nc, t, a.offsets, base, a.epoch, lane, a.ctl);
 }
 
 template <class T>

@@ -22,7 +22,6 @@ inline size_t max_chunk_bytes(falcon_dtype dt) {
   return dt == FALCON_FLOAT64 ? kF64Chunk : dt == FALCON_FLOAT32 ? kF32Chunk : 0;
 }
 inline uint64_t chunks_of(uint64_t n) { return (n + kChunkN - 1) / kChunkN; }
-inline uint64_t groups_of(uint64_t nchunks) { return (nchunks + 63) / 64; }
 inline uint32_t rd32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
 inline uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
 inline falcon_status dev_err(hipError_t e) { return e == hipSuccess ? FALCON_OK : FALCON_ERR_DEVICE; }
@@ -31,14 +30,15 @@ inline falcon_status dev_err(hipError_t e) { return e == hipSuccess ? FALCON_OK 
 void write_header(uint8_t* h, falcon_dtype dt, uint64_t n, uint64_t payload);
 
 // One independent launch queue: a stream and the device scratch that a
-// compression or decompression launch needs for itself (look-back status
-// words, control block).  Launches on different lanes may run concurrently.
+// compression or decompression launch needs for itself (chunk offsets,
+// scan tile sums, size-pass results, control block).  Launches on
+// different lanes may run concurrently.
 struct Lane {
   hipStream_t stream = nullptr;
-  uint64_t* status = nullptr;   // one word per chunk (compress: look-back; decompress: offsets)
-  size_t status_cap = 0;
-  uint64_t* gstatus = nullptr;  // one word per 64-chunk group, plus scan tile sums
-  size_t gstatus_cap = 0;
+  uint64_t* offsets = nullptr;  // one per chunk: exclusive prefix of the chunk sizes
+  size_t offsets_cap = 0;
+  uint64_t* tiles = nullptr;    // scan tile sums
+  size_t tiles_cap = 0;
   falcon_dev::Ctl* ctl = nullptr;
   uint8_t* stage = nullptr;     // pinned host bytes: [0,32) header, [32,36) error word, [40,48) payload size
   uint32_t epoch = 0;
@@ -77,7 +77,7 @@ struct BatchGeom {
 struct BatchLayout {
   int op = 0;
   size_t count = 0;
-  uint64_t total = 0, t64 = 0, groups = 0;
+  uint64_t total = 0, t64 = 0;
   bool has64 = false, has32 = false;
   falcon_dev::CompressSeries one_c{};
   falcon_dev::DecompressSeries one_d{};
@@ -91,10 +91,10 @@ struct BatchScratch {
   size_t many_cap = 0;
   uint8_t* h_desc = nullptr;     // pinned host copy of the descriptors
   size_t h_desc_cap = 0;
-  uint64_t* status = nullptr;
-  size_t status_cap = 0;
-  uint64_t* gstatus = nullptr;
-  size_t gstatus_cap = 0;
+  uint64_t* offsets = nullptr;   // chunk offsets (scan of all chunk sizes)
+  size_t offsets_cap = 0;
+  uint64_t* tiles = nullptr;
+  size_t tiles_cap = 0;
   uint32_t* sizes = nullptr;     // decompression: gathered chunk sizes; compression: chunk sizes
   size_t sizes_cap = 0;
   falcon_dev::ChunkMeta* meta = nullptr;  // compression size pass results

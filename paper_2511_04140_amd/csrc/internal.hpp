@@ -7,15 +7,11 @@
 
 namespace falcon_dev {
 
-// Control block of one launch: ticket counter handing out chunks in order,
-// exit counter (the last wave out resets both, so the next launch finds them
-// at zero), and an error word that receives the launch epoch when a chunk
-// fails a check.
+// Control block of a decompression launch: an error word that receives the
+// launch epoch when a chunk fails a check.
 struct Ctl {
-  uint32_t ticket;
-  uint32_t exited;
   uint32_t error;
-  uint32_t pad;
+  uint32_t pad[3];
 };
 
 // One array to compress.  chunk0 is the global index of its first chunk in
@@ -25,7 +21,6 @@ struct CompressSeries {
   uint8_t* out;
   uint64_t n;
   uint64_t chunk0;
-  uint64_t group0;   // index of the series' first 64-chunk group status word
   uint32_t dtype;    // 1 = f32, 2 = f64
   uint32_t idx;      // position of the series in the caller's list (lens[idx])
 };
@@ -35,7 +30,6 @@ struct DecompressSeries {
   uint8_t* out;
   uint64_t n;
   uint64_t chunk0;
-  uint64_t group0;
   uint64_t payload_bytes;  // batch launches: filled on the device from the stream header
   uint64_t in_len;         // stream bytes (batch launches)
   uint32_t dtype;
@@ -52,21 +46,18 @@ struct ChunkMeta {
 };
 
 struct CompressArgs {
-  CompressSeries one;            // used when nseries == 1
-  const CompressSeries* many;    // device array, sorted by chunk0, when nseries > 1
+  CompressSeries one;            // the series of a one-series launch (many == null)
+  const CompressSeries* many;    // device array, sorted by chunk0, for batch launches
   uint32_t nseries;
   uint32_t total_waves;
   uint64_t total_chunks;  // chunks of this launch: launch chunks t0 .. t0 + total_chunks - 1
   uint64_t t0;
-  uint64_t* status;    // one word per chunk of the launch
-  uint64_t* gstatus;   // one word per 64-chunk group of each series
-  Ctl* ctl;
   uint64_t* lens;      // batch launches: stream length of each series (device), else null
-  ChunkMeta* meta;     // two-pass compression: one per launch chunk
-  uint32_t* gsizes;    // two-pass compression: chunk sizes by launch chunk (scan input)
-  const uint64_t* offsets;  // two-pass compression: exclusive prefix of gsizes
-  uint32_t epoch;
+  ChunkMeta* meta;     // one per launch chunk, written by the size pass
+  uint32_t* gsizes;    // chunk sizes by launch chunk (scan input), written by the size pass
+  const uint64_t* offsets;  // exclusive prefix of gsizes, read by the write pass
   uint32_t relative;   // 1: offsets run over all series; a series subtracts its first one
+  uint32_t pad;
 };
 
 struct DecompressArgs {
@@ -76,7 +67,7 @@ struct DecompressArgs {
   uint32_t total_waves;
   uint64_t total_chunks;
   uint64_t t0;
-  const uint64_t* status;  // chunk offsets (exclusive prefix of the sizes)
+  const uint64_t* offsets;  // chunk offsets (exclusive prefix of the sizes)
   Ctl* ctl;
   uint32_t epoch;
   uint32_t relative;       // 1: offsets run over all series; a series subtracts its first one
@@ -89,14 +80,11 @@ constexpr int kDecompressWaves = 4;   // wavefronts per decompression workgroup
 // one (3) that takes either dtype per series.  nw = wavefronts per
 // compression workgroup, 8 or 16.
 constexpr int kFormMixed = 3;
-// pass 0: the single-pass kernel (decoupled look-back, chunk tickets);
-// pass 1: the size pass of two-pass compression (meta, gsizes and the
-// series' size arrays); pass 2: its write pass, after a scan of gsizes into
-// offsets.
+// pass 1: the size pass of compression (meta, gsizes and the series' size
+// arrays); pass 2: the write pass, after a scan of gsizes into offsets.
 hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s);
 // per-form entry points (one translation unit each)
-// pass: 0 = single-pass look-back kernel, 1 = size pass, 2 = write pass
 hipError_t launch_compress_f64(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_compress_f32(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_compress_mixed(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);

@@ -7,8 +7,7 @@ namespace falcon_dev {
 template <int NW>
 static hipError_t launch_nw(const CompressArgs& a, int pass, int grid, hipStream_t s) {
   if (pass == 1) hipLaunchKernelGGL((k_compress_pass<TF64, NW, 1>), dim3(grid), dim3(64 * NW), 0, s, a);
-  else if (pass == 2) hipLaunchKernelGGL((k_compress_pass<TF64, NW, 2>), dim3(grid), dim3(64 * NW), 0, s, a);
-  else hipLaunchKernelGGL((k_compress<TF64, NW>), dim3(grid), dim3(64 * NW), 0, s, a);
+  else hipLaunchKernelGGL((k_compress_pass<TF64, NW, 2>), dim3(grid), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
@@ -24,8 +23,7 @@ hipError_t launch_decompress_f64(const DecompressArgs& a, int grid, hipStream_t 
 template <int NW>
 static const void* kernel_nw(int pass) {
   if (pass == 1) return reinterpret_cast<const void*>(&k_compress_pass<TF64, NW, 1>);
-  if (pass == 2) return reinterpret_cast<const void*>(&k_compress_pass<TF64, NW, 2>);
-  return reinterpret_cast<const void*>(&k_compress<TF64, NW>);
+  return reinterpret_cast<const void*>(&k_compress_pass<TF64, NW, 2>);
 }
 
 const void* compress_kernel_f64(int pass, int nw) { return nw == 8 ? kernel_nw<8>(pass) : kernel_nw<16>(pass); }

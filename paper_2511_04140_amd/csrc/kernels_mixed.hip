@@ -24,8 +24,7 @@ __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4)
 template <int NW>
 static hipError_t launch_nw(const CompressArgs& a, int pass, int grid, hipStream_t s) {
   if (pass == 1) hipLaunchKernelGGL((k_compress_pass_mixed<NW, 1>), dim3(grid), dim3(64 * NW), 0, s, a);
-  else if (pass == 2) hipLaunchKernelGGL((k_compress_pass_mixed<NW, 2>), dim3(grid), dim3(64 * NW), 0, s, a);
-  else hipLaunchKernelGGL(k_compress_mixed<NW>, dim3(grid), dim3(64 * NW), 0, s, a);
+  else hipLaunchKernelGGL((k_compress_pass_mixed<NW, 2>), dim3(grid), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
@@ -41,8 +40,7 @@ hipError_t launch_decompress_mixed(const DecompressArgs& a, int grid, hipStream_
 template <int NW>
 static const void* kernel_nw(int pass) {
   if (pass == 1) return reinterpret_cast<const void*>(&k_compress_pass_mixed<NW, 1>);
-  if (pass == 2) return reinterpret_cast<const void*>(&k_compress_pass_mixed<NW, 2>);
-  return reinterpret_cast<const void*>(&k_compress_mixed<NW>);
+  return reinterpret_cast<const void*>(&k_compress_pass_mixed<NW, 2>);
 }
 
 const void* compress_kernel_mixed(int pass, int nw) { return nw == 8 ? kernel_nw<8>(pass) : kernel_nw<16>(pass); }

@@ -2,7 +2,7 @@
 // event-driven scheduler) on HIP streams.
 //
 // Compression: the input is cut into batches of whole chunks.  Each of N_s
-// lanes (a stream with its own device buffers and look-back scratch) runs
+// lanes (a stream with its own device buffers and launch scratch) runs
 // H2D -> compression kernel -> copy of the batch's payload byte count
 // (M-D2H), then, once the host has seen that count and every earlier batch
 // has been placed, the copy of the batch's sizes and payload to their final
