@@ -278,15 +278,17 @@ __device__ __forceinline__ void load_chunk(const CompressSeries& sd, uint64_t c,
 
 struct ChunkPlanes {
   uint32_t lo[16], hi[16];  // bit planes after the transpose (see plane_field)
+  uint64_t or0, or1;        // OR of this lane's elements 0-7 and 8-15 (size pass)
   uint64_t z1;
   int A, B;
   uint32_t w;
 };
 
 // a4-a7 once the chunk's case is known (cp.A, cp.B set): Eq. 3, Eq. 4, bit
-// width, transpose.  vb is consumed (free for the next chunk's loads when
-// this returns).
-template <class T>
+// width, and the transpose (TRANSPOSE) or, for the size pass, only the ORs
+// of each byte's eight elements (which decide whether a row byte is zero).
+// vb is consumed (free for the next chunk's loads when this returns).
+template <class T, bool TRANSPOSE = true>
 __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t* buf,
                                                    const typename T::U (&vb)[17], int lane_in, bool case1,
                                                    ChunkPlanes& cp) {
@@ -349,6 +351,17 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
     cp.w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
   }
 
+  if constexpr (!TRANSPOSE) {
+    U o0 = 0, o1 = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      o0 |= e[q];
+      o1 |= e[8 + q];
+    }
+    cp.or0 = (uint64_t)o0;
+    cp.or1 = (uint64_t)o1;
+    return;
+  }
   // a7: bit-plane transpose; element q of the lane goes to row q ^ 7 so that
   // the first element of each byte lands in its most significant bit.
 #pragma unroll
@@ -361,12 +374,12 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
 }
 
 // a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
-template <class T>
+template <class T, bool TRANSPOSE = true>
 __device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
                                                int lane, ChunkPlanes& cp) {
   bool case1;
   decide_case<T>(sm, vb, cp.A, cp.B, case1);
-  compress_transform<T>(sm, buf, vb, lane, case1, cp);
+  compress_transform<T, TRANSPOSE>(sm, buf, vb, lane, case1, cp);
 }
 
 // a8-a9: per-row non-zero byte counts (sparse iff more than 16 of the 128
@@ -386,6 +399,30 @@ __device__ __forceinline__ ChunkStats chunk_stats(const ChunkPlanes& cp) {
     if (p < (int)w) {
       const uint32_t fld = plane_field<T, p>(cp.lo, cp.hi);
       const uint64_t E = ballot((fld & 0xFFu) != 0), O = ballot((fld & 0xFF00u) != 0);
+      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+      const bool dense = nnz >= 112;
+      flags |= (uint64_t)dense << p;
+      rows += dense ? 128u : 16u + nnz;
+    }
+  });
+  ChunkStats st;
+  st.flags = flags;
+  st.S = 3 + T::ZB + ((w + 7) >> 3) + rows;
+  return st;
+}
+
+// a8-a9 from the byte ORs of the size pass: byte 2L of row p (elements
+// 16L..16L+7, plane p) is non-zero iff bit p of or0 is set; byte 2L+1 the
+// same with or1.  Gives the same flags and size as chunk_stats.
+template <class T>
+__device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp) {
+  const uint32_t w = cp.w;
+  uint64_t flags = 0;
+  uint32_t rows = 0;
+  for_planes_down<T::W - 1>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p < (int)w) {
+      const uint64_t E = ballot(((cp.or0 >> p) & 1) != 0), O = ballot(((cp.or1 >> p) & 1) != 0);
       const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
       const bool dense = nnz >= 112;
       flags |= (uint64_t)dense << p;
@@ -480,45 +517,102 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dst, u
 // ---------------------------------------------------------------------------
 // Decompression of one chunk (Sec. 4, executed by one wave)
 // ---------------------------------------------------------------------------
+// A chunk's payload on its way from HBM to LDS: lane L holds the 16-byte
+// blocks L, L + 64, ... of the payload's 16-byte-aligned span (pad = offset
+// of the payload's first byte in the first block).  Loading the next chunk
+// into these registers while the current one is decoded hides the load
+// latency.
+// Eight blocks per lane cover payload spans up to 8192 bytes; the few
+// blocks beyond (only nearly all-dense float64 chunks reach them) are read
+// when the payload is stored into LDS.
+constexpr int kStageBlocks = 8;
+
+struct Staged {
+  uint4 blk[kStageBlocks];
+  const uint8_t* sal;  // 16-byte-aligned start of the payload span
+  uint64_t avail;      // readable bytes from sal
+  uint32_t S, pad, total;
+  bool bad;
+};
+
+// Block i of a staged span: whole, or byte by byte where it would pass the
+// end of the readable bytes.
+__device__ __forceinline__ uint4 load_block(const uint8_t* sal, uint64_t avail, uint32_t i) {
+  if (16ull * i + 16 <= avail) return *reinterpret_cast<const uint4*>(sal + 16 * i);
+  uint32_t wv[4] = {0, 0, 0, 0};
+  for (uint32_t b = 0; b < 16 && 16ull * i + b < avail; ++b) wv[b >> 2] |= (uint32_t)sal[16 * i + b] << (8 * (b & 3));
+  return make_uint4(wv[0], wv[1], wv[2], wv[3]);
+}
+
+// d1 and the payload loads of launch chunk t of series sd.  The chunk
+// offset comes from the prefix scan of the size array (k_scan_*); in a
+// batch launch the scan runs over the sizes of all series and a series
+// subtracts the offset of its first chunk.  Every size must lie in
+// [3 + ZB, BOUND] of the series' dtype and the series' sizes must add up to
+// its payload byte count (checked by its last chunk); a chunk that fails
+// loads nothing.  Blocks are read whole, except a last block that would
+// pass the end of the payload, which is read byte by byte.
+__device__ __forceinline__ Staged stage_issue(const DecompressSeries& sd, uint64_t t, const uint64_t* offsets,
+                                              bool relative, int lane_in) {
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
+  Staged st;
+  const uint64_t c = t - sd.chunk0;
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  const bool f64 = sd.dtype == 2;
+  const uint32_t lo = f64 ? (uint32_t)TF64::ZB + 3 : (uint32_t)TF32::ZB + 3;
+  const uint32_t hi = f64 ? (uint32_t)TF64::BOUND : (uint32_t)TF32::BOUND;
+  const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
+  st.S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
+  const uint64_t base = relative ? uniform64(offsets[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(offsets[t]) - base;
+  st.bad = st.S > hi || st.S < lo || off + st.S > sd.payload_bytes ||
+           (c == nc - 1 && off + st.S != sd.payload_bytes);
+  st.pad = 0;
+  st.total = 0;
+  st.sal = payload;
+  st.avail = 0;
+  if (!st.bad) {
+    const uint8_t* src = payload + off;
+    st.pad = uniform((uint32_t)((uintptr_t)src & 15u));
+    st.total = st.pad + st.S;
+    st.sal = src - st.pad;
+    st.avail = (uint64_t)(payload + sd.payload_bytes - st.sal);
+    const uint32_t nblk = (st.total + 15) >> 4;
+#pragma unroll
+    for (int k = 0; k < kStageBlocks; ++k) {
+      const uint32_t i = (uint32_t)lane + 64u * k;
+      if (i < nblk) st.blk[k] = load_block(st.sal, st.avail, i);
+    }
+  }
+  return st;
+}
+
+// Moves a staged payload into the wave's LDS buffer.
+__device__ __forceinline__ void stage_store(uint8_t* buf, const Staged& st, int lane) {
+  const uint32_t nblk = (st.total + 15) >> 4;
+#pragma unroll
+  for (int k = 0; k < kStageBlocks; ++k) {
+    const uint32_t i = (uint32_t)lane + 64u * k;
+    if (i < nblk) *reinterpret_cast<uint4*>(buf + 16 * i) = st.blk[k];
+  }
+  for (uint32_t i = (uint32_t)lane + 64u * kStageBlocks; i < nblk; i += 64)
+    *reinterpret_cast<uint4*>(buf + 16 * i) = load_block(st.sal, st.avail, i);
+}
+
+// d2-d5 of one chunk whose payload is in LDS (stage_store done).
 template <class T>
 __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* buf, const DecompressSeries& sd,
-                                                 uint64_t c, uint64_t nc, uint64_t t, const uint64_t* offsets,
-                                                 uint64_t off_base, uint32_t epoch, int lane_in, Ctl* ctl) {
+                                                 uint64_t c, uint32_t S, uint32_t pad, uint32_t total, bool bad,
+                                                 uint32_t epoch, int lane_in, Ctl* ctl) {
   using U = typename T::U;
   using F = typename T::F;
   using S_ = typename T::S;
   int lane = lane_in;  // opaque, see compress_front
   asm volatile("" : "+v"(lane));
-  const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
-  const uint32_t S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
-  // d1: chunk offset, from the prefix scan of the size array (k_scan_*).
-  // In a batch launch the scan runs over the sizes of all series and a
-  // series subtracts the offset of its first chunk (off_base).  Every size
-  // must lie in [3 + ZB, BOUND] and the series' sizes must add up to its
-  // payload byte count (checked by its last chunk).
-  const uint64_t off = uniform64(offsets[t]) - off_base;
-  bool bad = S > (uint32_t)T::BOUND || S < (uint32_t)(3 + T::ZB) || off + S > sd.payload_bytes ||
-             (c == nc - 1 && off + S != sd.payload_bytes);
   if (bad) {
     if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
-  }
-  // stage the payload bytes in LDS at their 16-byte phase
-  const uint8_t* src = payload + off;
-  const uint32_t pad = uniform((uint32_t)((uintptr_t)src & 15u));
-  const uint32_t total = uniform(pad + S);
-  {
-    const uint8_t* sal = src - pad;
-    const uint32_t nblk = (total + 15) >> 4;
-    for (uint32_t i = lane; i < nblk; i += 64) {
-      const uint32_t b_lo = i << 4, b_hi = b_lo + 16;
-      if (b_lo >= pad && b_hi <= total) {
-        *reinterpret_cast<uint4*>(buf + b_lo) = *reinterpret_cast<const uint4*>(sal + b_lo);
-      } else {
-        const uint32_t from = b_lo > pad ? b_lo : pad, to = b_hi < total ? b_hi : total;
-        for (uint32_t b = from; b < to; ++b) buf[b] = sal[b];
-      }
-    }
   }
   wave_lds_sync();
   // chunk header: alpha_max, beta_hat_max, z_1, w, scheme flags
@@ -688,8 +782,8 @@ __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, c
   const uint64_t c = t - sd.chunk0;
   load_chunk<T>(sd, c, lane, vb);
   ChunkPlanes cp;
-  compress_front<T>(tab, buf, vb, lane, cp);
-  const ChunkStats st = chunk_stats<T>(cp);
+  compress_front<T, false>(tab, buf, vb, lane, cp);
+  const ChunkStats st = chunk_stats_or<T>(cp);
   if (lane == 0) {
     ChunkMeta m;
     m.flags = st.flags;
@@ -782,28 +876,47 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 }
 
 // Decompression has no dependence between chunks once the offsets are
-// known, so waves take chunks by static striding and use no counter.
-template <class T>
-__device__ __forceinline__ void decompress_one(const LdsTables& tab, uint8_t* buf, const DecompressArgs& a,
-                                               const DecompressSeries& sd, uint64_t t, int lane) {
-  const uint64_t c = t - sd.chunk0;
-  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-  const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
-  decompress_chunk<T>(tab, buf, sd, c, nc, t, a.offsets, base, a.epoch, lane, a.ctl);
+// known, so waves take chunks by static striding and use no counter.  Each
+// wave loads the payload of its next chunk into registers while it decodes
+// the current one; dispatch(series, c, S, pad, total, bad) decodes the chunk
+// just staged into LDS.
+template <class Dispatch>
+__device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t* buf, int lane, int wid,
+                                                Dispatch&& dispatch) {
+  uint64_t t = (uint64_t)blockIdx.x * kWavesD + wid;
+  if (t >= a.total_chunks) return;
+  DecompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
+  Staged st = stage_issue(sd, t + a.t0, a.offsets, a.relative != 0, lane);
+  for (;;) {
+    stage_store(buf, st, lane);
+    const DecompressSeries cur = sd;
+    const uint64_t c = t + a.t0 - cur.chunk0;
+    const uint32_t S = st.S, pad = st.pad, total = st.total;
+    const bool bad = st.bad;
+    const uint64_t tn = t + a.total_waves;
+    const bool more = tn < a.total_chunks;
+    if (more) {
+      sd = find_series(a.one, a.many, a.nseries, tn + a.t0);
+      st = stage_issue(sd, tn + a.t0, a.offsets, a.relative != 0, lane);
+    }
+    dispatch(cur, c, S, pad, total, bad);
+    if (!more) break;
+    t = tn;
+  }
 }
 
 template <class T>
-__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
+__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(3))) void k_decompress(DecompressArgs a) {
   __shared__ BlockLdsT<kWavesD> sm;
   load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();
-  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  const uint64_t w0 = (uint64_t)blockIdx.x * kWavesD + (threadIdx.x >> 6);
-  for (uint64_t t = w0; t < a.total_chunks; t += a.total_waves) {
-    const uint64_t tg = t + a.t0;
-    decompress_one<T>(sm.tab, buf, a, find_series(a.one, a.many, a.nseries, tg), tg, lane);
-  }
+  const int wid = threadIdx.x >> 6;
+  uint8_t* buf = wave_bytes(sm, wid);
+  decompress_loop(a, buf, lane, wid,
+                  [&](const DecompressSeries& sd, uint64_t c, uint32_t S, uint32_t pad, uint32_t total, bool bad) {
+                    decompress_chunk<T>(sm.tab, buf, sd, c, S, pad, total, bad, a.epoch, lane, a.ctl);
+                  });
 }
 
 }  // namespace falcon_dev

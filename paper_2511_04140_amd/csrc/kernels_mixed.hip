@@ -11,14 +11,15 @@ __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4)
   load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();
-  uint8_t* buf = wave_bytes(sm, threadIdx.x >> 6);
-  const uint64_t w0 = (uint64_t)blockIdx.x * kWavesD + (threadIdx.x >> 6);
-  for (uint64_t t = w0; t < a.total_chunks; t += a.total_waves) {
-    const uint64_t tg = t + a.t0;
-    const DecompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
-    if (uniform(sd.dtype) == 2) decompress_one<TF64>(sm.tab, buf, a, sd, tg, lane);
-    else decompress_one<TF32>(sm.tab, buf, a, sd, tg, lane);
-  }
+  const int wid = threadIdx.x >> 6;
+  uint8_t* buf = wave_bytes(sm, wid);
+  decompress_loop(a, buf, lane, wid,
+                  [&](const DecompressSeries& sd, uint64_t c, uint32_t S, uint32_t pad, uint32_t total, bool bad) {
+                    if (uniform(sd.dtype) == 2)
+                      decompress_chunk<TF64>(sm.tab, buf, sd, c, S, pad, total, bad, a.epoch, lane, a.ctl);
+                    else
+                      decompress_chunk<TF32>(sm.tab, buf, sd, c, S, pad, total, bad, a.epoch, lane, a.ctl);
+                  });
 }
 
 template <int NW>
