@@ -631,62 +631,44 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
     for (uint32_t f = 0; f < nflag; ++f)
       flags = (flags << 8) | (uint32_t)__builtin_amdgcn_readlane((int)hb, 3 + T::ZB + (int)f);
   }
-  // d2: rows -> bit-plane fields of this lane (row bytes 2L, 2L+1)
+  // d2: rows -> bit-plane fields of this lane (row bytes 2L, 2L+1).  The
+  // row cursor and the error flag are wave-uniform; reads use clamped
+  // addresses so that a corrupt stream never reads outside the buffer (its
+  // result is discarded through the flag).
   uint32_t lo[16], hi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) lo[i] = hi[i] = 0;
   uint32_t cur = uniform(pad + 3 + T::ZB + nflag);
-  const int q = lane >> 2, u2 = 2 * (lane & 3);
+  bool ubad = uniform((uint32_t)bad) != 0;
+  constexpr uint32_t kLim = kWaveLds - 1;
+  const uint32_t sh = 6u - 2u * ((uint32_t)lane & 3u);  // bitmap bit of row byte 2L + 1
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
-    cur = uniform(cur);
-    if (!bad && p < (int)w) {
-      uint32_t fld = 0;
+    if (p < (int)w) {
+      uint32_t fld;
       if ((flags >> p) & 1) {
-        if (cur + 128 > total) {
-          bad = true;
-        } else {
-          fld = (uint32_t)buf[cur + 2 * lane] | ((uint32_t)buf[cur + 2 * lane + 1] << 8);
-          cur += 128;
-        }
-      } else if (cur + 16 > total) {
-        bad = true;
+        ubad |= cur + 128 > total;
+        const uint32_t a0 = min(cur + 2 * (uint32_t)lane, kLim - 1);
+        fld = (uint32_t)buf[a0] | ((uint32_t)buf[a0 + 1] << 8);
+        cur += 128;
       } else {
-        // 16-byte bitmap at an arbitrary byte offset: five aligned dwords
-        const uint32_t a0 = cur & ~3u, sh = (cur & 3u) * 8;
-        const uint32_t* d = reinterpret_cast<const uint32_t*>(buf + a0);
-        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-        // every lane read the same bytes: make the bitmap wave-uniform so
-        // that the row cursor stays a scalar
-        const uint32_t m0 = uniform(sh ? (d0 >> sh) | (d1 << (32 - sh)) : d0);
-        const uint32_t m1 = uniform(sh ? (d1 >> sh) | (d2 << (32 - sh)) : d1);
-        const uint32_t m2 = uniform(sh ? (d2 >> sh) | (d3 << (32 - sh)) : d2);
-        const uint32_t m3 = uniform(sh ? (d3 >> sh) | (d4 << (32 - sh)) : d3);
-        const uint32_t p0 = __popc(m0), p1 = __popc(m1), p2 = __popc(m2), p3 = __popc(m3);
-        const uint32_t nnz = p0 + p1 + p2 + p3;
-        if (cur + 16 + nnz > total) {
-          bad = true;
-        } else {
-          const int di = q >> 2, bi = q & 3;
-          const uint32_t md = di == 0 ? m0 : di == 1 ? m1 : di == 2 ? m2 : m3;
-          const uint32_t before = (di > 0 ? p0 : 0) + (di > 1 ? p1 : 0) + (di > 2 ? p2 : 0) +
-                                  (uint32_t)__popc(md & ((1u << (8 * bi)) - 1u));
-          const uint32_t byteq = (md >> (8 * bi)) & 0xFFu;
-          const uint32_t nz0 = (byteq >> (7 - u2)) & 1u, nz1 = (byteq >> (6 - u2)) & 1u;
-          const uint32_t rank = before + (uint32_t)__popc(byteq >> (8 - u2));
-          // both reads stay inside the row's data bytes or the buffer slack
-          const uint32_t r0 = buf[cur + 16 + rank], r1 = buf[cur + 16 + rank + nz0];
-          const uint32_t b0 = nz0 ? r0 : 0u;
-          const uint32_t b1 = nz1 ? r1 : 0u;
-          fld = b0 | (b1 << 8);
-          cur += 16 + nnz;
-        }
+        ubad |= cur + 16 > total;
+        // bitmap byte L/4 covers this lane's row bytes 2L and 2L+1 (MSB first)
+        const uint32_t bm = buf[min(cur + ((uint32_t)lane >> 2), kLim)];
+        const uint32_t nz0 = (bm >> (sh + 1)) & 1u, nz1 = (bm >> sh) & 1u;
+        const uint64_t E = ballot(nz0 != 0), O = ballot(nz1 != 0);
+        const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+        const uint32_t rank = mbcnt(E) + mbcnt(O);
+        const uint32_t d0 = cur + 16 + rank;
+        const uint32_t r0 = buf[min(d0, kLim)], r1 = buf[min(d0 + nz0, kLim)];
+        fld = (nz0 ? r0 : 0u) | ((nz1 ? r1 : 0u) << 8);
+        ubad |= cur + 16 + nnz > total;
+        cur += 16 + nnz;
       }
       plane_put<p>(lo, hi, fld);
     }
   });
-  if (cur != total) bad = true;
-  if (bad) {
+  if (ubad || cur != total) {
     if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wave_lds_sync();
     return;
