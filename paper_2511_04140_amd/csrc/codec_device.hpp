@@ -156,58 +156,100 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int m) {
-  return (uint32_t)__shfl_xor((int)v, m, 64);
+// Cross-lane data movement inside rows of 16 lanes with DPP (a VALU operand
+// modifier, no LDS round trip).  Controls (GFX9 encoding): quad_perm
+// [1,0,3,2] = 0xB1 and [2,3,0,1] = 0x4E swap lanes at distance 1 and 2;
+// row_half_mirror (0x141) and row_mirror (0x140) reverse 8- and 16-lane
+// halves; row_shr:k (0x110 + k) shifts right by k inside the row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  uint32_t lo = shfl_xor32((uint32_t)v, m), hi = shfl_xor32((uint32_t)(v >> 32), m);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
-  uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d, 64);
-  uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d, 64);
-  return ((uint64_t)hi << 32) | lo;
+// row_shr:K with lanes that have no source reading 0.
+template <int K>
+__device__ __forceinline__ uint32_t dpp_shr0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + K, 0xF, 0xF, true);
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v += shfl_xor64(v, m);
+// OR over the 16 lanes of each row, delivered to every lane of the row.
+__device__ __forceinline__ uint32_t row_or32(uint32_t v) {
+  v |= dpp<kDppXor1>(v);
+  v |= dpp<kDppXor2>(v);
+  v |= dpp<kDppHalfMirror>(v);
+  v |= dpp<kDppMirror>(v);
   return v;
 }
-__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) {
-    uint64_t o = shfl_xor64(v, m);
-    v = o > v ? o : v;
-  }
-  return v;
+__device__ __forceinline__ uint32_t rl(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// Wave-wide OR (uniform result).
+__device__ __forceinline__ uint32_t wave_or32(uint32_t v) {
+  v = row_or32(v);
+  return rl(v, 0) | rl(v, 16) | rl(v, 32) | rl(v, 48);
 }
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v |= shfl_xor64(v, m);
-  return v;
+  return ((uint64_t)wave_or32((uint32_t)(v >> 32)) << 32) | wave_or32((uint32_t)v);
 }
-__device__ __forceinline__ uint32_t wave_or32(uint32_t v) {
+
+// Wave-wide unsigned maximum (uniform result).
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
+  auto step = [&](auto ctrl_tag) {
+    constexpr int C = decltype(ctrl_tag)::value;
+    const uint64_t o = ((uint64_t)dpp<C>((uint32_t)(v >> 32)) << 32) | dpp<C>((uint32_t)v);
+    v = o > v ? o : v;
+  };
+  step(std::integral_constant<int, kDppXor1>{});
+  step(std::integral_constant<int, kDppXor2>{});
+  step(std::integral_constant<int, kDppHalfMirror>{});
+  step(std::integral_constant<int, kDppMirror>{});
+  uint64_t m = 0;
 #pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v |= shfl_xor32(v, m);
-  return v;
+  for (int r = 0; r < 4; ++r) {
+    const uint64_t x = ((uint64_t)rl((uint32_t)(v >> 32), 16 * r) << 32) | rl((uint32_t)v, 16 * r);
+    m = x > m ? x : m;
+  }
+  return m;
 }
 __device__ __forceinline__ int wave_max_i32(int v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) {
-    int o = __shfl_xor(v, m, 64);
+  auto step = [&](auto ctrl_tag) {
+    constexpr int C = decltype(ctrl_tag)::value;
+    const int o = (int)dpp<C>((uint32_t)v);
     v = o > v ? o : v;
-  }
-  return v;
-}
-// Inclusive prefix sum over lanes (Hillis-Steele), modulo 2^64.
-__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, int lane) {
+  };
+  step(std::integral_constant<int, kDppXor1>{});
+  step(std::integral_constant<int, kDppXor2>{});
+  step(std::integral_constant<int, kDppHalfMirror>{});
+  step(std::integral_constant<int, kDppMirror>{});
+  int m = (int)rl((uint32_t)v, 0);
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t o = shfl_up64(v, d);
-    if (lane >= d) v += o;
+  for (int r = 1; r < 4; ++r) {
+    const int x = (int)rl((uint32_t)v, 16 * r);
+    m = x > m ? x : m;
   }
-  return v;
+  return m;
+}
+
+// Inclusive prefix sum over lanes, modulo 2^64: a scan inside each row of
+// 16 lanes (row_shr 1, 2, 4, 8), then the totals of the rows below added
+// from scalar registers.
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, int lane) {
+  auto step = [&](auto k_tag) {
+    constexpr int K = decltype(k_tag)::value;
+    const uint64_t o = ((uint64_t)dpp_shr0<K>((uint32_t)(v >> 32)) << 32) | dpp_shr0<K>((uint32_t)v);
+    v += o;
+  };
+  step(std::integral_constant<int, 1>{});
+  step(std::integral_constant<int, 2>{});
+  step(std::integral_constant<int, 4>{});
+  step(std::integral_constant<int, 8>{});
+  auto row_total = [&](int r) {
+    return ((uint64_t)rl((uint32_t)(v >> 32), 16 * r + 15) << 32) | rl((uint32_t)v, 16 * r + 15);
+  };
+  const uint64_t t0 = row_total(0), t1 = row_total(1), t2 = row_total(2);
+  const int row = lane >> 4;
+  const uint64_t below = row == 0 ? 0 : row == 1 ? t0 : row == 2 ? t0 + t1 : t0 + t1 + t2;
+  return v + below;
 }
 // Number of set bits of mask in lanes below this one.
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {

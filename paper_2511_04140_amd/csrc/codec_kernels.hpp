@@ -344,10 +344,10 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
 #pragma unroll
   for (int q = 0; q < 16; ++q) orv |= e[q];
   if constexpr (sizeof(U) == 8) {
-    const uint64_t o = uniform64(wave_or64((uint64_t)orv));
+    const uint64_t o = wave_or64((uint64_t)orv);
     cp.w = o ? 64u - (uint32_t)__builtin_clzll(o) : 0u;
   } else {
-    const uint32_t o = uniform(wave_or32((uint32_t)orv));
+    const uint32_t o = wave_or32((uint32_t)orv);
     cp.w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
   }
 
@@ -469,8 +469,8 @@ __device__ __forceinline__ void assemble_payload(uint8_t* buf, const ChunkPlanes
         const uint64_t E = ballot(b0 != 0), O = ballot(b1 != 0);
         // bitmap byte q covers row bytes 8q..8q+7, i.e. lanes 4q..4q+3
         uint32_t bits = (((b0 != 0) ? 2u : 0u) | ((b1 != 0) ? 1u : 0u)) << (6 - 2 * (lane & 3));
-        bits |= shfl_xor32(bits, 1);
-        bits |= shfl_xor32(bits, 2);
+        bits |= dpp<kDppXor1>(bits);
+        bits |= dpp<kDppXor2>(bits);
         if ((lane & 3) == 0) buf[cur + (lane >> 2)] = (uint8_t)bits;
         const uint32_t rank = mbcnt(E) + mbcnt(O);
         if (b0) buf[cur + 16 + rank] = (uint8_t)b0;
