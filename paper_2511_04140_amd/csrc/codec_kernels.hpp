@@ -181,13 +181,26 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
       return;
     }
   } else {
+    // A failing value whose own limit equals L* is an exception.  Its limit
+    // min(AMAX, BMAX - 1 - FL10(|v|)) equals L* exactly when L* = AMAX or
+    // FL10(|v|) = FL10(v_max), i.e. |v| >= fl(10^FL10(v_max)): one compare,
+    // tried for all failing values before any full test.
+    const U thr = T::u(T::pow10(sm, maxfl));
     bool e = false;
+    if (lstar == T::AMAX) {
+      e = fail != 0;
+    } else {
 #pragma unroll
-    for (int k = 0; k < 17; ++k) {
-      if ((fail >> k) & 1u) {
-        const int f = fl10<T>(sm, T::mag(vb[k]));
-        const int lim = min(T::AMAX, T::BMAX - 1 - f);
-        if (lim == lstar || !full_test<T>(vb[k], T::pow10(sm, lim))) e = true;
+      for (int k = 0; k < 17; ++k) e |= ((fail >> k) & 1u) && T::mag(vb[k]) >= thr;
+    }
+    if (!ballot(e)) {
+#pragma unroll
+      for (int k = 0; k < 17; ++k) {
+        if ((fail >> k) & 1u) {
+          const int f = fl10<T>(sm, T::mag(vb[k]));
+          const int lim = min(T::AMAX, T::BMAX - 1 - f);
+          if (lim == lstar || !full_test<T>(vb[k], T::pow10(sm, lim))) e = true;
+        }
       }
     }
     if (ballot(e)) {

@@ -160,3 +160,23 @@ def test_fast_decision_matches_literal_alg2(orc, dt, count):
             mismatches.append((ch[:4], got, (A, B)))
     assert not mismatches, mismatches[:5]
     assert literal < count // 5
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_own_limit_shortcut(dt):
+    """The GPU first tests a failing value's own limit against L* with one
+    magnitude compare: lim_i == L* exactly when L* == AMAX or
+    |v_i| >= fl(10^FL10(v_max)).  Checked here for random magnitudes and
+    maxima over the whole admissible range."""
+    spec = Spec(dt)
+    rng = np.random.default_rng(7 + (dt == np.float32))
+    lo, hi = spec.bits(spec.P[-spec.A])[()], spec.bits(spec.P[spec.B])[()]
+    for _ in range(400):
+        vmax = rng.integers(lo, hi, dtype=spec.U, endpoint=False)
+        m = rng.integers(lo, vmax, 64, dtype=spec.U, endpoint=True)
+        maxfl = int(spec.fl10(np.array([vmax], spec.U))[0])
+        lstar = min(spec.A, spec.B - 1 - maxfl)
+        lim = np.minimum(spec.A, spec.B - 1 - spec.fl10(m))
+        thr = spec.bits(spec.P[maxfl])[()]
+        shortcut = np.full(m.shape, lstar == spec.A) | (m >= thr)
+        assert np.array_equal(lim == lstar, shortcut)
