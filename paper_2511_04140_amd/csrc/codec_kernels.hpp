@@ -770,14 +770,18 @@ __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
 // at its offset.  No chunk ever waits for another, so waves take chunks by
 // static striding.
 // ---------------------------------------------------------------------------
-template <class T>
+// vb holds the chunk's values when loaded is set (else they are loaded
+// here); prefetch() runs as soon as vb is free, so that the next chunk's
+// loads overlap the rest of this one.
+template <class T, class Prefetch>
 __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
                                            const CompressSeries& sd, uint64_t t, int lane,
-                                           typename T::U (&vb)[17]) {
+                                           typename T::U (&vb)[17], bool loaded, Prefetch&& prefetch) {
   const uint64_t c = t - sd.chunk0;
-  load_chunk<T>(sd, c, lane, vb);
+  if (!loaded) load_chunk<T>(sd, c, lane, vb);
   ChunkPlanes cp;
   compress_front<T, false>(tab, buf, vb, lane, cp);
+  prefetch();
   const ChunkStats st = chunk_stats_or<T>(cp);
   if (lane == 0) {
     ChunkMeta m;
@@ -794,13 +798,13 @@ __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, c
   wave_lds_sync();
 }
 
-template <class T>
+template <class T, class Prefetch>
 __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
                                             const CompressSeries& sd, uint64_t t, int lane,
-                                            typename T::U (&vb)[17]) {
+                                            typename T::U (&vb)[17], bool loaded, Prefetch&& prefetch) {
   const uint64_t c = t - sd.chunk0;
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
-  load_chunk<T>(sd, c, lane, vb);
+  if (!loaded) load_chunk<T>(sd, c, lane, vb);
   const uint64_t* mp = reinterpret_cast<const uint64_t*>(a.meta + t);
   const uint64_t flags = uniform64(mp[0]);
   const uint64_t m1 = uniform64(mp[1]);
@@ -809,6 +813,7 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   cp.A = (int)((m1 >> 32) & 0xFF);
   cp.B = (int)((m1 >> 40) & 0xFF);
   compress_transform<T>(tab, buf, vb, lane, cp.A <= T::AMAX && cp.B <= T::BMAX, cp);
+  prefetch();
   assemble_payload<T>(buf, cp, flags, S, lane);
   const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
   const uint64_t off = uniform64(a.offsets[t]) - base;
@@ -839,11 +844,25 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   typename T::U vb[17];
   if (PASS == 2 && a.total_chunks == 0 && !a.many && blockIdx.x == 0 && wid == 0)
     write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
-  for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
+  uint64_t t = (uint64_t)blockIdx.x * NW + wid;
+  if (t >= a.total_chunks) return;
+  CompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
+  load_chunk<T>(sd, t + a.t0 - sd.chunk0, lane, vb);
+  for (;;) {
     const uint64_t tg = t + a.t0;
-    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
-    if (PASS == 1) size_chunk<T>(sm.tab, buf, a, sd, tg, lane, vb);
-    else write_chunk<T>(sm.tab, buf, a, sd, tg, lane, vb);
+    const CompressSeries cur = sd;
+    const uint64_t tn = t + a.total_waves;
+    const bool more = tn < a.total_chunks;
+    auto prefetch = [&]() {
+      if (more) {
+        sd = find_series(a.one, a.many, a.nseries, tn + a.t0);
+        load_chunk<T>(sd, tn + a.t0 - sd.chunk0, lane, vb);
+      }
+    };
+    if (PASS == 1) size_chunk<T>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
+    else write_chunk<T>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
+    if (!more) break;
+    t = tn;
   }
 }
 
@@ -858,14 +877,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
     const uint64_t tg = t + a.t0;
     const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    auto none = []() {};
     if (uniform(sd.dtype) == 2) {
       uint64_t vb[17];
-      if (PASS == 1) size_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
-      else write_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb);
+      if (PASS == 1) size_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      else write_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     } else {
       uint32_t vb[17];
-      if (PASS == 1) size_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
-      else write_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb);
+      if (PASS == 1) size_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      else write_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     }
   }
 }
