@@ -334,13 +334,15 @@ def main():
             assert torch.equal(y.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
     torch.cuda.synchronize()
 
-    kc, kd = [], []
+    kc, kd, sc, sd_ = [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s = codec.compress(xd, out=sbuf)
         kc.append(codec.last_kernel_ms())
+        sc.append(codec.last_stage_ms())
         y = codec.decompress(s, out=ybuf)
         kd.append(codec.last_kernel_ms())
+        sd_.append(codec.last_stage_ms())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert torch.equal(ybuf.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
@@ -352,15 +354,24 @@ def main():
     ratio = clen / nbytes
     step_s = (t1 - t0) / args.steps
     kc_ms, kd_ms = float(np.mean(kc)), float(np.mean(kd))
+    nc = (x.size + 1024) // 1025
+    # kernels of the path: their average durations (HIP events) and the
+    # algorithmic bytes one launch moves
+    kernels = {
+        "k_compress_pass<size>": (float(np.mean([v[0] for v in sc])), nbytes + 4 * nc),
+        "k_scan (compress)": (float(np.mean([v[1] for v in sc])), 4 * nc + 8 * nc),
+        "k_compress_pass<write>": (float(np.mean([v[2] for v in sc])), nbytes + clen - 4 * nc),
+        "k_scan (decompress)": (float(np.mean([v[1] for v in sd_])), 4 * nc + 8 * nc),
+        "k_decompress": (float(np.mean([v[2] for v in sd_])), clen + nbytes),
+    }
+    dominant = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_bytes = kernels[dominant]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, dom_bytes)
     algo_c = nbytes + clen          # read the values, write the stream
     algo_d = clen + nbytes          # read the stream, write the values
-    dominant = "k_compress" if kc_ms >= kd_ms else "k_decompress"
-    dom_ms = max(kc_ms, kd_ms)
-    achieved = (algo_c if dominant == "k_compress" else algo_d) / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dominant, algo_c)
 
     # fraction of chunks in each case of Eq. 3 (header byte alpha_max <= 22)
-    nc = (x.size + 1024) // 1025
     sizes = s[32:32 + 4 * nc].view(torch.int32).to(torch.int64)
     offs = torch.cumsum(sizes, 0) - sizes
     a_bytes = s[32 + 4 * nc + offs]
@@ -386,7 +397,7 @@ def main():
         "decompress_gbps": round(nbytes / (kd_ms * 1e-3) / 1e9, 3),
         "ratio": round(ratio, 6),
         "case1_chunk_fraction": round(case1, 6),
-        "kernel_ms": {"k_compress": round(kc_ms, 4), "k_decompress": round(kd_ms, 4)},
+        "kernel_ms": {k: round(v[0], 4) for k, v in kernels.items()},
         "roofline": {
             "bound": "hbm",
             "kernel": dominant,
@@ -395,11 +406,15 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
+            "algorithmic_bytes": int(dom_bytes),
         },
-        "roofline_other": {
-            "kernel": "k_decompress" if dominant == "k_compress" else "k_compress",
-            "achieved": round((algo_d if dominant == "k_compress" else algo_c) /
-                              (min(kc_ms, kd_ms) * 1e-3) / 1e9, 2),
+        "roofline_ops": {
+            "compress (size pass + scan + write pass)": {
+                "ms": round(kc_ms, 4), "achieved": round(algo_c / (kc_ms * 1e-3) / 1e9, 2),
+                "frac": round(algo_c / (kc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+            "decompress (decoding kernel)": {
+                "ms": round(kd_ms, 4), "achieved": round(algo_d / (kd_ms * 1e-3) / 1e9, 2),
+                "frac": round(algo_d / (kd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         },
     }
     del sbuf, ybuf, s, y, xd

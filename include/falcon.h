@@ -265,11 +265,16 @@ void falcon_server_destroy(falcon_server* s);
  * a version-1 Falcon header. */
 falcon_status falcon_stream_info(const void* h_hdr, size_t len, size_t* n, falcon_dtype* dt);
 
-/* Duration in milliseconds of the last compression or decompression kernel
- * launched through ctx, measured with HIP events recorded on the launch
- * stream immediately before and after the kernel.  Intended for roofline
- * accounting; FALCON_ERR_INVALID_ARG if no kernel has run yet. */
+/* Device time in milliseconds of the last falcon_compress (its three
+ * stages: size pass, scan of the sizes, write pass) or falcon_decompress
+ * (its decoding kernel, after the scan of the size array), measured with
+ * HIP events recorded on the launch stream.  Intended for roofline
+ * accounting; FALCON_ERR_INVALID_ARG if no call has run yet. */
 falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms);
+
+/* The stages of that call separately, ms[0..2]: compression size pass,
+ * scan, write pass; decompression 0, scan, decoding kernel. */
+falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms);
 
 /* Static, human-readable name of a status code. */
 const char* falcon_status_str(falcon_status st);

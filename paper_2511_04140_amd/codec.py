@@ -86,6 +86,8 @@ def _load():
     L.falcon_stream_info.restype = i
     L.falcon_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.falcon_last_kernel_ms.restype = i
+    L.falcon_last_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.falcon_last_stage_ms.restype = i
     L.falcon_compress_host.argtypes = [vp, vp, sz, i, vp, sz, ctypes.POINTER(sz)]
     L.falcon_compress_host.restype = i
     L.falcon_decompress_host.argtypes = [vp, vp, sz, vp, sz, ctypes.POINTER(sz)]
@@ -179,6 +181,15 @@ class Codec:
         if st != 0:
             raise FalconError(st, "falcon_last_kernel_ms")
         return ms.value
+
+    def last_stage_ms(self) -> list:
+        """Stages of the last call: [size pass, scan, write pass] for
+        compression, [0, scan, decoding kernel] for decompression."""
+        ms = (ctypes.c_float * 3)()
+        st = lib().falcon_last_stage_ms(self._ctx, ms)
+        if st != 0:
+            raise FalconError(st, "falcon_last_stage_ms")
+        return [ms[0], ms[1], ms[2]]
 
     def compress(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Compresses a contiguous float32/float64 device tensor; returns the

@@ -115,22 +115,24 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.relative = 0;
   const int g1 = grid_for(max_grid_c(ctx, dt, 1, kCompressWaves), nc, kCompressWaves);
   const int g2 = grid_for(max_grid_c(ctx, dt, 2, kCompressWaves), nc, kCompressWaves);
-  if (timed) {
-    ctx->timed = false;
-    if ((st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
-  }
+  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
+  if (timed) ctx->timed = false;
+  if ((st = mark(0)) != FALCON_OK) return st;
   if (nc) {
     a.total_waves = (uint32_t)(g1 * kCompressWaves);
     if ((st = dev_err(launch_compress(a, (int)dt, 1, kCompressWaves, g1, s))) != FALCON_OK) return st;
-    if ((st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch, s))) !=
-        FALCON_OK)
-      return st;
   }
+  if ((st = mark(1)) != FALCON_OK) return st;
+  if (nc && (st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch, s))) !=
+                FALCON_OK)
+    return st;
+  if ((st = mark(2)) != FALCON_OK) return st;
   a.total_waves = (uint32_t)(g2 * kCompressWaves);
   if ((st = dev_err(launch_compress(a, (int)dt, 2, kCompressWaves, g2, s))) != FALCON_OK) return st;
+  if ((st = mark(3)) != FALCON_OK) return st;
   if (timed) {
-    if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
     ctx->timed = true;
+    ctx->timed_compress = true;
   }
   return FALCON_OK;
 }
@@ -144,7 +146,9 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   // checks: every size in [lo, hi], their sum equal to the payload bytes).
   const uint32_t lo = dt == FALCON_FLOAT64 ? 11u : 7u;
   const uint32_t hi = (uint32_t)max_chunk_bytes(dt);
+  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
   if (timed) ctx->timed = false;
+  if ((st = mark(0)) != FALCON_OK || (st = mark(1)) != FALCON_OK) return st;
   if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi, payload, l.tiles,
                                       l.offsets, l.ctl, l.epoch, s))) != FALCON_OK)
     return st;
@@ -164,11 +168,12 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   a.relative = 0;
   const int grid = grid_for(max_grid_d(ctx, dt), nc, kDecompressWaves);
   a.total_waves = (uint32_t)(grid * kDecompressWaves);
-  if (timed && (st = dev_err(hipEventRecord(ctx->ev0, s))) != FALCON_OK) return st;
+  if ((st = mark(2)) != FALCON_OK) return st;
   if ((st = dev_err(launch_decompress(a, (int)dt, grid, s))) != FALCON_OK) return st;
+  if ((st = mark(3)) != FALCON_OK) return st;
   if (timed) {
-    if ((st = dev_err(hipEventRecord(ctx->ev1, s))) != FALCON_OK) return st;
     ctx->timed = true;
+    ctx->timed_compress = false;
   }
   return dev_err(hipMemcpyAsync(l.stage + 32, &l.ctl->error, 4, hipMemcpyDeviceToHost, s));
 }
@@ -206,8 +211,9 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
   falcon_ctx* ctx = new (std::nothrow) falcon_ctx();
   if (!ctx) return FALCON_ERR_OUT_OF_MEMORY;
   ctx->device = device;
-  if (lane_init(ctx->main) != FALCON_OK || hipEventCreate(&ctx->ev0) != hipSuccess ||
-      hipEventCreate(&ctx->ev1) != hipSuccess) {
+  if (lane_init(ctx->main) != FALCON_OK || hipEventCreate(&ctx->ev[0]) != hipSuccess ||
+      hipEventCreate(&ctx->ev[1]) != hipSuccess || hipEventCreate(&ctx->ev[2]) != hipSuccess ||
+      hipEventCreate(&ctx->ev[3]) != hipSuccess) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
@@ -229,8 +235,8 @@ void falcon_destroy(falcon_ctx* ctx) {
   if (ctx->main.stream) (void)hipStreamSynchronize(ctx->main.stream);
   batch_free(ctx->batch);
   lane_free(ctx->main);
-  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -298,8 +304,16 @@ falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len
 
 falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms) {
   if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
-  if (hipEventSynchronize(ctx->ev1) != hipSuccess) return FALCON_ERR_DEVICE;
-  return dev_err(hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
+  if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
+  return dev_err(hipEventElapsedTime(ms, ctx->ev[ctx->timed_compress ? 0 : 2], ctx->ev[3]));
+}
+
+falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms) {
+  if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
+  if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
+  for (int i = 0; i < 3; ++i)
+    if (hipEventElapsedTime(ms + i, ctx->ev[i], ctx->ev[i + 1]) != hipSuccess) return FALCON_ERR_DEVICE;
+  return FALCON_OK;
 }
 
 }  // extern "C"

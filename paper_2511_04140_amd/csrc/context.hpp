@@ -116,8 +116,11 @@ struct falcon_ctx {
   // and workgroup size (8 or 16 waves)
   int grid_c[4][3][2] = {};
   int grid_d[4] = {};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last timed kernel
+  // events of the last timed call: before the first kernel, after it, after
+  // the scan, after the last kernel (decompression: the first two coincide)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
+  bool timed_compress = false;
   // host <-> device pipeline
   int pipe_streams = 16;
   uint64_t pipe_batch_chunks = 4096;
