@@ -535,10 +535,11 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dst, u
 // of the payload's first byte in the first block).  Loading the next chunk
 // into these registers while the current one is decoded hides the load
 // latency.
-// Eight blocks per lane cover payload spans up to 8192 bytes; the few
-// blocks beyond (only nearly all-dense float64 chunks reach them) are read
-// when the payload is stored into LDS.
-constexpr int kStageBlocks = 8;
+// Six blocks per lane cover payload spans up to 6144 bytes and keep the
+// kernel within 128 VGPRs (4 waves per SIMD); the blocks beyond (mostly
+// dense float64 chunks reach them) are read when the payload is stored
+// into LDS.
+constexpr int kStageBlocks = 6;
 
 struct Staged {
   uint4 blk[kStageBlocks];
@@ -921,7 +922,7 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
 }
 
 template <class T>
-__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(3))) void k_decompress(DecompressArgs a) {
+__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
   __shared__ BlockLdsT<kWavesD> sm;
   load_tables(sm.tab);
   __syncthreads();
