@@ -703,30 +703,42 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   }
   const uint64_t incl = wave_incl_scan64((uint64_t)run, lane);
   const U basev = (U)(z1 + (U)(incl - (uint64_t)run));
-  // d5: inverse Eq. 3, then coalesced store of the first nv values
-  const bool case1 = A <= T::AMAX && B <= T::BMAX;
-  const F P = T::pow10(sm, case1 ? A : 0);
+  // d5: inverse Eq. 3 (a uniform branch on the chunk's case), then
+  // coalesced stores of the first nv values.  Store k covers elements
+  // 64k - mis .. 64k - mis + 63, where mis aligns it to 128-byte lines, so
+  // that only the two lines shared with the neighbouring chunks are written
+  // in part.
+  const bool case1 = uniform((uint32_t)(A <= T::AMAX && B <= T::BMAX)) != 0;
   wave_lds_sync();
   U* vals = reinterpret_cast<U*>(buf);
+  if (case1) {
+    const F P = T::pow10(sm, A);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const U gt = (U)(basev + gv[i]);
-    const U bits = case1 ? T::u((F)(S_)gt / P) : unzigzag<U>(gt);
-    const uint32_t idx = 16u * lane + 1 + i;
-    vals[idx + (idx >> 4)] = bits;
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t idx = 16u * lane + 1 + i;
+      vals[idx + (idx >> 4)] = T::u((F)(S_)(U)(basev + gv[i]) / P);
+    }
+    if (lane == 0) vals[0] = T::u((F)(S_)z1 / P);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t idx = 16u * lane + 1 + i;
+      vals[idx + (idx >> 4)] = unzigzag<U>((U)(basev + gv[i]));
+    }
+    if (lane == 0) vals[0] = unzigzag<U>(z1);
   }
-  const U v1 = case1 ? T::u((F)(S_)z1 / P) : unzigzag<U>(z1);
   wave_lds_sync();
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
-  const uint32_t nv = rem < (uint64_t)kChunk ? (uint32_t)rem : (uint32_t)kChunk;
+  const int nv = rem < (uint64_t)kChunk ? (int)rem : (int)kChunk;
   U* out = reinterpret_cast<U*>(sd.out) + base;
+  constexpr uint32_t kLine = 128 / sizeof(U);
+  const int mis = (int)(((uintptr_t)out / sizeof(U)) % kLine);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t i = 1 + 64 * k + lane;
-    if (i < nv) __builtin_nontemporal_store(vals[i + (i >> 4)], out + i);
+  for (int k = 0; k < 17; ++k) {
+    const int j = 64 * k + lane - mis;
+    if (j >= 0 && j < nv) __builtin_nontemporal_store(vals[j + (j >> 4)], out + j);
   }
-  if (lane == 0) out[0] = v1;
   wave_lds_sync();
 }
 
