@@ -51,7 +51,7 @@ def _inputs():
     ]
 
 
-@pytest.mark.parametrize("streams,batch", [(1, 4096), (3, 1), (4, 3), (16, 2), (16, 4096)])
+@pytest.mark.parametrize("streams,batch", [(1, 4096), (3, 1), (4, 3), (4, 1024), (16, 2), (16, 4096)])
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
 def test_pipeline_matches_oracle_and_device(codec, orc, streams, batch, pinned):
     codec.set_pipeline(streams, batch)
