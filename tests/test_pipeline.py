@@ -116,10 +116,10 @@ def test_pipeline_rejects_corrupt_streams(codec, orc):
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
 def test_pipeline_full_size_sensor_f64(codec, pinned):
     """The 2 GiB float64 workload host -> host with the default geometry
-    (16 streams, 4096-chunk batches): the stream equals the device-resident
+    (4 streams, 1024-chunk batches): the stream equals the device-resident
     one and decompresses to the input."""
     from paper_2511_04140_amd import workloads as W
-    codec.set_pipeline(16, 4096)
+    codec.set_pipeline()
     x = W.sensor_f64(1 << 28, seed=2)
     _log(f"[pipeline] full-size sensor_f64 pinned={pinned}")
     xh = _host(x, pinned)
