@@ -449,8 +449,7 @@ __device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp) {
 }
 
 // a11 (first half): the chunk payload (header bytes, scheme flags, rows) in
-// the wave's LDS buffer at offset 0, followed by zeroed slack so that the
-// aligned reads of copy_payload see defined bytes.
+// LDS at buf (any byte offset).
 template <class T>
 __device__ __forceinline__ void assemble_payload(uint8_t* buf, const ChunkPlanes& cp, uint64_t flags, uint32_t S,
                                                  int lane_in) {
@@ -492,37 +491,23 @@ __device__ __forceinline__ void assemble_payload(uint8_t* buf, const ChunkPlanes
       }
     }
   });
-  if (lane < 8) reinterpret_cast<uint32_t*>(buf)[((S + 3) >> 2) + lane] = 0u;
 }
 
-// a11 (second half): copies the S payload bytes from LDS to dst with aligned
-// 16-byte stores; byte stores only in the first and last block.
-__device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dst, uint32_t S, int lane) {
-  const uint32_t ph = (uint32_t)((uintptr_t)dst & 15u);
-  uint8_t* dal = dst - ph;
-  const uint32_t nblk = (ph + S + 15) >> 4;
-  const uint32_t rb = (16u - ph) & 3u;  // byte shift inside a dword
-  const uint32_t* bw = reinterpret_cast<const uint32_t*>(buf);
+// a11 (second half): copies a payload assembled in LDS at byte phase ph
+// (buf + ph holds its S bytes, ph = the destination's offset inside its
+// 16-byte block) to dal + ph, dal being 16-byte aligned: whole blocks with
+// one 16-byte LDS read and one 16-byte store each, the partial first and
+// last blocks byte by byte.
+__device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dal, uint32_t ph, uint32_t S, int lane) {
+  const uint32_t end = ph + S;
+  const uint32_t nblk = (end + 15) >> 4;
   for (uint32_t k = lane; k < nblk; k += 64) {
-    const bool edge = (k == 0 && ph != 0) || (16 * k + 16 > ph + S);
-    if (!edge) {
-      // payload bytes [16k - ph, 16k - ph + 16) from dwords starting at q
-      const uint32_t q = (16 * k - ph) >> 2;
-      const uint32_t d0 = bw[q], d1 = bw[q + 1], d2 = bw[q + 2], d3 = bw[q + 3], d4 = bw[q + 4];
-      uint4 v;
-      if (rb == 0) {
-        v = make_uint4(d0, d1, d2, d3);
-      } else {
-        v.x = __builtin_amdgcn_alignbyte(d1, d0, rb);
-        v.y = __builtin_amdgcn_alignbyte(d2, d1, rb);
-        v.z = __builtin_amdgcn_alignbyte(d3, d2, rb);
-        v.w = __builtin_amdgcn_alignbyte(d4, d3, rb);
-      }
-      *reinterpret_cast<uint4*>(dal + 16 * k) = v;
+    const uint32_t b_lo = 16 * k, b_hi = b_lo + 16;
+    if (b_lo >= ph && b_hi <= end) {
+      *reinterpret_cast<uint4*>(dal + b_lo) = *reinterpret_cast<const uint4*>(buf + b_lo);
     } else {
-      const uint32_t from = 16 * k > ph ? 16 * k : ph;
-      const uint32_t to = 16 * k + 16 < ph + S ? 16 * k + 16 : ph + S;
-      for (uint32_t b = from; b < to; ++b) dal[b] = buf[b - ph];
+      const uint32_t from = b_lo > ph ? b_lo : ph, to = b_hi < end ? b_hi : end;
+      for (uint32_t b = from; b < to; ++b) dal[b] = buf[b];
     }
   }
 }
@@ -827,11 +812,15 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   cp.B = (int)((m1 >> 40) & 0xFF);
   compress_transform<T>(tab, buf, vb, lane, cp.A <= T::AMAX && cp.B <= T::BMAX, cp);
   prefetch();
-  assemble_payload<T>(buf, cp, flags, S, lane);
+  // the payload goes to dst; it is assembled at dst's 16-byte phase so that
+  // the copy moves whole aligned blocks
   const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
   const uint64_t off = uniform64(a.offsets[t]) - base;
+  uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
+  const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
+  assemble_payload<T>(buf + ph, cp, flags, S, lane);
   wave_lds_sync();
-  copy_payload(buf, sd.out + kHdrBytes + 4 * nc + off, S, lane);
+  copy_payload(buf, dst - ph, ph, S, lane);
   if (c == nc - 1) {
     write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
     if (a.lens && lane == 0) a.lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
