@@ -383,7 +383,9 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
     cp.hi[i] = sizeof(U) == 8 ? (uint32_t)((uint64_t)e[i ^ 7] >> 32) : 0u;
   }
   xpose16(cp.lo);
-  if constexpr (sizeof(U) == 8) xpose16(cp.hi);
+  // with w <= 32 every upper half is zero, and so is its transpose
+  if constexpr (sizeof(U) == 8)
+    if (cp.w > 32) xpose16(cp.hi);
 }
 
 // a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
@@ -674,7 +676,8 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   }
   // d3: inverse transpose
   xpose16(lo);
-  if constexpr (sizeof(U) == 8) xpose16(hi);
+  if constexpr (sizeof(U) == 8)
+    if (w > 32) xpose16(hi);  // planes 32..63 absent: hi stays zero
   // d4: un-zigzag and prefix sum from g_1 = z_1 (modulo 2^W)
   U gv[16];
   U run = 0;
