@@ -121,6 +121,176 @@ def host_pipeline(codec, x, torch, reps=2):
     return res
 
 
+def batched(codec, torch, reps=5):
+    """10,000 series of uneven lengths and mixed dtypes (about 4 GB),
+    device-resident: the one-series-per-launch loop (falcon_compress /
+    falcon_decompress per series) against one tuned, graph-captured batch
+    plan over all of them; both write to buffers of their own and must give
+    identical bytes."""
+    import ctypes
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    dev = codec.device
+    xs = W.batch_series()
+    align = lambda v: (v + 255) // 256 * 256
+    in_off, out_off, bounds = [], [], []
+    ti = to = 0
+    for x in xs:
+        in_off.append(ti)
+        ti += align(x.nbytes)
+        b = C.compress_bound(x.size, torch.float64 if x.dtype == np.float64 else torch.float32)
+        bounds.append(b)
+        out_off.append(to)
+        to += align(b)
+    host = np.zeros(ti, np.uint8)
+    for x, o in zip(xs, in_off):
+        host[o:o + x.nbytes] = x.view(np.uint8)
+    xin = torch.from_numpy(host).to(dev)
+    del host
+    tdt = lambda x: torch.float64 if x.dtype == np.float64 else torch.float32
+    xv = [xin[o:o + x.nbytes].view(tdt(x)) for x, o in zip(xs, in_off)]
+    outs = {k: torch.zeros(to, dtype=torch.uint8, device=dev) for k in ("loop", "plan")}
+    ov = {k: [outs[k][o:o + b] for o, b in zip(out_off, bounds)] for k in outs}
+    raw = sum(x.nbytes for x in xs)
+    L = C.lib()
+    olen = ctypes.c_size_t()
+    sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    cargs = [(ctypes.c_void_p(v.data_ptr()), v.numel(), C._dtype_code(v.dtype), ctypes.c_void_p(o.data_ptr()),
+              o.numel()) for v, o in zip(xv, ov["loop"])]
+
+    def loop_compress():
+        lens = []
+        for a in cargs:
+            st = L.falcon_compress(codec._ctx, a[0], a[1], a[2], a[3], a[4], ctypes.byref(olen), sh)
+            assert st == 0
+            lens.append(olen.value)
+        return lens
+
+    torch.cuda.synchronize()
+    loop_compress()
+    t0 = time.perf_counter()
+    lens = loop_compress()
+    t_loop = time.perf_counter() - t0
+    plan = codec.plan_compress(xv, outs=ov["plan"], tune=True, graph=True)
+    info = plan.info()
+    plan.run(fetch=False)
+    tp = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        plan.run(fetch=False)
+        tp.append(time.perf_counter() - t0)
+    streams = plan.run()
+    identical = [s.numel() for s in streams] == lens and torch.equal(outs["loop"], outs["plan"])
+    clen = sum(lens)
+    # decompression of the same streams
+    dv = {k: torch.zeros(ti, dtype=torch.uint8, device=dev) for k in ("loop", "plan")}
+    dviews = {k: [dv[k][o:o + x.nbytes].view(tdt(x)) for x, o in zip(xs, in_off)] for k in dv}
+    nout = ctypes.c_size_t()
+    dargs = [(ctypes.c_void_p(s.data_ptr()), s.numel(), ctypes.c_void_p(y.data_ptr()), y.numel() * y.element_size())
+             for s, y in zip(streams, dviews["loop"])]
+
+    def loop_decompress():
+        for a in dargs:
+            st = L.falcon_decompress(codec._ctx, a[0], a[1], a[2], a[3], ctypes.byref(nout), sh)
+            assert st == 0
+
+    loop_decompress()
+    t0 = time.perf_counter()
+    loop_decompress()
+    t_dloop = time.perf_counter() - t0
+    dplan = codec.plan_decompress(streams, [x.size for x in xs], [tdt(x) for x in xs], outs=dviews["plan"],
+                                  tune=True, graph=True)
+    dinfo = dplan.info()
+    dplan.run(fetch=False)
+    td = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dplan.run(fetch=False)
+        td.append(time.perf_counter() - t0)
+    identical = identical and torch.equal(dv["loop"], dv["plan"]) and torch.equal(dv["plan"], xin)
+    sizes = sorted(x.size for x in xs)
+    res = {
+        "series": len(xs), "f64_series": int(sum(x.dtype == np.float64 for x in xs)),
+        "values_min_median_max": [sizes[0], sizes[len(sizes) // 2], sizes[-1]],
+        "bytes": raw, "ratio": round(clen / raw, 6),
+        "timing": "wall clock around each call; the per-series loop calls the C ABI once per series "
+                  "through ctypes, the batch plan replays one HIP graph",
+        "compress": {"per_series_gbps": round(raw / t_loop / 1e9, 3),
+                     "batched_gbps": round(raw / min(tp) / 1e9, 3),
+                     "speedup": round(t_loop / min(tp), 2),
+                     "plan": {k: info[k] for k in ("split", "waves_per_group", "grid_percent", "candidates")}},
+        "decompress": {"per_series_gbps": round(raw / t_dloop / 1e9, 3),
+                       "batched_gbps": round(raw / min(td) / 1e9, 3),
+                       "speedup": round(t_dloop / min(td), 2),
+                       "plan": {k: dinfo[k] for k in ("split", "grid_percent", "candidates")}},
+        "identical": bool(identical),
+    }
+    plan.close()
+    dplan.close()
+    return res
+
+
+def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
+    """Poisson arrivals, 70% compress / 30% decompress, payloads 4 KB-64 MB
+    log-uniform, float32/float64: the served loop (continuous batching over
+    4 streams) against the plain FIFO (one request per launch), both at the
+    same offered load, rho times the FIFO's measured saturation rate."""
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    dev = codec.device
+    ps = W.serving_payloads()
+    pd = [torch.from_numpy(p).to(dev) for p in ps]
+    streams = [codec.compress(p).clone() for p in pd]
+    rng = np.random.default_rng([6, 0])
+    is_c = rng.random(n_req) < 0.7
+    idx = rng.integers(0, len(ps), n_req)
+    nbytes = np.array([p.nbytes for p in ps])
+    total_bytes = int(nbytes[idx].sum())
+
+    def run(srv, arrivals):
+        got = []
+        t_start = time.perf_counter()
+        base_us = None
+        for i in range(n_req):
+            if arrivals is not None:
+                t_next = t_start + arrivals[i]
+                while time.perf_counter() < t_next:
+                    for c in srv.poll(0):
+                        srv.release(c)
+                        got.append(c)
+            k = int(idx[i])
+            if is_c[i]:
+                srv.submit_compress(pd[k], tag=i)
+            else:
+                srv.submit_decompress(streams[k], pd[k].numel(), pd[k].dtype, tag=i)
+        while len(got) < n_req:
+            for c in srv.poll(20):
+                srv.release(c)
+                got.append(c)
+        assert all(c["status"] == 0 for c in got)
+        lat = np.array([c["complete_us"] - c["submit_us"] for c in got])
+        span = (max(c["complete_us"] for c in got) - min(c["submit_us"] for c in got)) * 1e-6
+        return {"p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "mean_us": round(float(lat.mean()), 1), "gbps": round(total_bytes / span / 1e9, 3),
+                "req_per_s": round(n_req / span, 1)}
+
+    res = {"requests": n_req, "payloads": len(ps), "mean_payload_mb": round(float(nbytes.mean()) / 1e6, 3),
+           "rho": rho, "hbm_budget_gib": budget >> 30}
+    cfgs = {"fifo": dict(lanes=1, max_batch=1), "served": dict(lanes=4, max_batch=256)}
+    servers = {k: C.Server(codec, hbm_budget=budget if k == "served" else budget // 2, **v)
+               for k, v in cfgs.items()}
+    sat = {k: run(s, None) for k, s in servers.items()}
+    lam = rho * sat["fifo"]["req_per_s"]
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    res["offered_req_per_s"] = round(lam, 1)
+    for k, s in servers.items():
+        res[k] = {"saturation": sat[k], "at_offered_load": run(s, arrivals)}
+        s.close()
+    return res
+
+
 def codec_bound(x):
     from paper_2511_04140_amd import codec as C
     import torch
