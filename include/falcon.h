@@ -129,6 +129,29 @@ falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t i
  * destroyed.  FALCON_ERR_INVALID_ARG outside the ranges. */
 falcon_status falcon_set_pipeline(falcon_ctx* ctx, int n_streams, size_t batch_chunks);
 
+/* The three schedulers of the compression pipeline that Sec. 3.1 compares
+ * (Fig. 5, Fig. 12a).  All give the same stream, byte for byte.
+ *  EVENT_DRIVEN   Alg. 1 (the default): each lane polls its events, and a
+ *                 lane places its payload once its byte count has arrived
+ *                 and every batch launched before it has been placed.
+ *  SYNC_BASED     Fig. 5b: the host waits for each batch's byte count
+ *                 (M-D2H) before it launches the next batch; only the
+ *                 payload copy (P-D2H) of a batch overlaps the next batch.
+ *  PRE_ALLOCATION Fig. 5a: every batch copies its whole worst-case output
+ *                 region into a fixed slot of a pinned host buffer (about
+ *                 falcon_compress_bound of the input, kept by the context
+ *                 until the geometry changes or the context is destroyed),
+ *                 and a host merge packs the slots into h_out. */
+typedef enum falcon_scheduler {
+  FALCON_SCHED_EVENT_DRIVEN = 0,
+  FALCON_SCHED_SYNC_BASED = 1,
+  FALCON_SCHED_PRE_ALLOCATION = 2
+} falcon_scheduler;
+
+/* Selects the scheduler falcon_compress_host uses (decompression always uses
+ * pre-allocation, Sec. 4).  FALCON_ERR_INVALID_ARG for another value. */
+falcon_status falcon_set_pipeline_scheduler(falcon_ctx* ctx, falcon_scheduler kind);
+
 /* ---- Many series in one launch ----------------------------------------
  * One series of a batch call or plan.  Compression: d_in holds n values of
  * type dtype (device), d_out (device, out_cap bytes, 4-byte aligned) receives

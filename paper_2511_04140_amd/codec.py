@@ -19,6 +19,7 @@ FALCON_FLOAT32 = 1
 FALCON_FLOAT64 = 2
 _STATUS = {0: "ok", 1: "invalid argument", 2: "buffer too small", 3: "corrupt stream",
            4: "device error", 5: "out of memory"}
+ERR_INVALID_ARG = 1
 ERR_BUFFER_TOO_SMALL = 2
 ERR_CORRUPT_STREAM = 3
 
@@ -63,6 +64,7 @@ OP_COMPRESS = 0
 OP_DECOMPRESS = 1
 PLAN_TUNE = 1
 PLAN_GRAPH = 2
+SCHEDULERS = {"event": 0, "sync": 1, "prealloc": 2}
 
 
 def _load():
@@ -94,6 +96,8 @@ def _load():
     L.falcon_decompress_host.restype = i
     L.falcon_set_pipeline.argtypes = [vp, i, sz]
     L.falcon_set_pipeline.restype = i
+    L.falcon_set_pipeline_scheduler.argtypes = [vp, i]
+    L.falcon_set_pipeline_scheduler.restype = i
     ps = ctypes.POINTER(Series)
     L.falcon_compress_batch.argtypes = [vp, ps, sz, vp]
     L.falcon_compress_batch.restype = i
@@ -239,6 +243,14 @@ class Codec:
         st = lib().falcon_set_pipeline(self._ctx, n_streams, batch_chunks)
         if st != 0:
             raise FalconError(st, "falcon_set_pipeline")
+
+    def set_scheduler(self, kind: str = "event"):
+        """Compression scheduler of the pipeline: "event" (Alg. 1),
+        "sync" (Sync-Based) or "prealloc" (Pre-Allocation)."""
+        code = SCHEDULERS[kind]
+        st = lib().falcon_set_pipeline_scheduler(self._ctx, code)
+        if st != 0:
+            raise FalconError(st, "falcon_set_pipeline_scheduler")
 
     def compress_host(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Compresses a contiguous float32/float64 host tensor through the

@@ -128,6 +128,9 @@ struct falcon_ctx {
   uint64_t pipe_batch_chunks = 1024;
   size_t pipe_buf_bytes = 0;     // bytes of each g_in / g_out / p_in / p_out
   bool pipe_staging = false;     // p_in / p_out allocated
+  int pipe_scheduler = 0;        // falcon_scheduler of compression
+  uint8_t* pre_buf = nullptr;    // pinned per-batch slots of the pre-allocation scheduler
+  size_t pre_cap = 0;
   std::vector<falcon_host::PipeLane> pipe;
   // one-shot batch calls
   falcon_host::BatchScratch batch;

@@ -108,6 +108,9 @@ void pipe_release(falcon_ctx* ctx) {
   ctx->pipe.clear();
   ctx->pipe_buf_bytes = 0;
   ctx->pipe_staging = false;
+  if (ctx->pre_buf) (void)hipHostFree(ctx->pre_buf);
+  ctx->pre_buf = nullptr;
+  ctx->pre_cap = 0;
 }
 
 }  // namespace falcon_host
@@ -125,6 +128,216 @@ falcon_status falcon_set_pipeline(falcon_ctx* ctx, int n_streams, size_t batch_c
   ctx->pipe_batch_chunks = batch_chunks;
   return FALCON_OK;
 }
+
+namespace {
+
+struct CompressJob {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n, nc, bc, nbatch, payload_base;
+  falcon_dtype dt;
+  size_t es;
+  bool in_pinned, out_pinned;
+};
+
+// H2D of batch b and its compression into p.g_out on p's stream; with
+// m_d2h, the copy of the batch's payload byte count to p.lane.stage + 40.
+falcon_status issue_batch(falcon_ctx* ctx, PipeLane& p, const CompressJob& j, uint64_t b, bool m_d2h) {
+  hipStream_t s = p.lane.stream;
+  p.c0 = b * j.bc;
+  p.nchunks = j.nc - p.c0 < j.bc ? j.nc - p.c0 : j.bc;
+  const uint64_t v0 = p.c0 * kChunkN;
+  p.nvals = j.n - v0 < p.nchunks * kChunkN ? j.n - v0 : p.nchunks * kChunkN;
+  const uint8_t* src = j.in + v0 * j.es;
+  if (!j.in_pinned) {
+    memcpy(p.p_in, src, p.nvals * j.es);
+    src = p.p_in;
+  }
+  falcon_status st;
+  if ((st = dev_err(hipMemcpyAsync(p.g_in, src, p.nvals * j.es, hipMemcpyHostToDevice, s))) != FALCON_OK ||
+      (st = enqueue_compress(ctx, p.lane, p.g_in, p.nvals, j.dt, p.g_out, s, false)) != FALCON_OK)
+    return st;
+  if (m_d2h) return dev_err(hipMemcpyAsync(p.lane.stage + 40, p.g_out + 24, 8, hipMemcpyDeviceToHost, s));
+  return FALCON_OK;
+}
+
+// P-D2H: the batch's sizes and its cs payload bytes to their final place
+// (payload at offset), or to the lane's pinned staging for pageable output.
+falcon_status issue_placement(PipeLane& p, const CompressJob& j, uint64_t offset) {
+  hipStream_t s = p.lane.stream;
+  p.dst = offset;
+  const uint8_t* sizes = p.g_out + 32;
+  falcon_status st;
+  if (j.out_pinned) {
+    if ((st = dev_err(hipMemcpyAsync(j.out + 32 + 4 * p.c0, sizes, 4 * p.nchunks, hipMemcpyDeviceToHost, s))) !=
+        FALCON_OK)
+      return st;
+    return dev_err(
+        hipMemcpyAsync(j.out + j.payload_base + offset, sizes + 4 * p.nchunks, p.cs, hipMemcpyDeviceToHost, s));
+  }
+  return dev_err(hipMemcpyAsync(p.p_out, sizes, 4 * p.nchunks + p.cs, hipMemcpyDeviceToHost, s));
+}
+
+// After the placement copies: the host copies of staged output.
+void finish_placement(const PipeLane& p, const CompressJob& j) {
+  if (j.out_pinned) return;
+  memcpy(j.out + 32 + 4 * p.c0, p.p_out, 4 * p.nchunks);
+  memcpy(j.out + j.payload_base + p.dst, p.p_out + 4 * p.nchunks, p.cs);
+}
+
+falcon_status read_cs(PipeLane& p, const CompressJob& j) {
+  p.cs = rd64(p.lane.stage + 40);
+  return p.cs > p.nchunks * max_chunk_bytes(j.dt) ? FALCON_ERR_DEVICE : FALCON_OK;
+}
+
+// Alg. 1 (event-driven): lanes cycle Idle -> MPend -> PPend -> Idle; a lane
+// in MPend places its payload once its byte count has arrived and every
+// batch launched before it has been placed (launch order is kept in a
+// queue, which is what Alg. 1's `current` stands for).
+falcon_status compress_event_driven(falcon_ctx* ctx, const CompressJob& j, uint64_t* total) {
+  const int ns = (int)ctx->pipe.size();
+  std::vector<int> order(j.nbatch);
+  uint64_t next = 0, placed = 0, done = 0, offset = 0;
+  falcon_status st;
+  for (auto& p : ctx->pipe) p.state = kIdle;
+  while (done < j.nbatch) {
+    bool moved = false;
+    for (int i = 0; i < ns; ++i) {
+      PipeLane& p = ctx->pipe[i];
+      if (p.state == kIdle) {
+        if (next >= j.nbatch) continue;
+        const uint64_t b = next++;
+        if ((st = issue_batch(ctx, p, j, b, true)) != FALCON_OK ||
+            (st = dev_err(hipEventRecord(p.ev, p.lane.stream))) != FALCON_OK)
+          return st;
+        order[b] = i;
+        p.state = kMPend;
+        moved = true;
+      } else if (p.state == kMPend) {
+        if (order[placed] != i) continue;  // not the current lane yet
+        const int r = poll(p);
+        if (r < 0) return FALCON_ERR_DEVICE;
+        if (r == 0) continue;
+        if ((st = read_cs(p, j)) != FALCON_OK || (st = issue_placement(p, j, offset)) != FALCON_OK ||
+            (st = dev_err(hipEventRecord(p.ev, p.lane.stream))) != FALCON_OK)
+          return st;
+        offset += p.cs;
+        ++placed;
+        p.state = kPPend;
+        moved = true;
+      } else {  // kPPend
+        const int r = poll(p);
+        if (r < 0) return FALCON_ERR_DEVICE;
+        if (r == 0) continue;
+        finish_placement(p, j);
+        ++done;
+        p.state = kIdle;
+        moved = true;
+      }
+    }
+    if (!moved) std::this_thread::yield();
+  }
+  *total = offset;
+  return FALCON_OK;
+}
+
+// Sync-Based Scheduler (Sec. 3.1, Fig. 5b): the host waits for each batch's
+// byte count before it launches the next batch; only the payload copy of a
+// batch overlaps the transfer and compression of the next.
+falcon_status compress_sync_based(falcon_ctx* ctx, const CompressJob& j, uint64_t* total) {
+  const int ns = (int)ctx->pipe.size();
+  uint64_t offset = 0;
+  falcon_status st;
+  for (auto& p : ctx->pipe) p.state = kIdle;
+  for (uint64_t b = 0; b < j.nbatch; ++b) {
+    PipeLane& p = ctx->pipe[b % ns];
+    if (p.state == kPPend) {
+      if (hipEventSynchronize(p.ev) != hipSuccess) return FALCON_ERR_DEVICE;
+      finish_placement(p, j);
+    }
+    if ((st = issue_batch(ctx, p, j, b, true)) != FALCON_OK ||
+        (st = dev_err(hipEventRecord(p.ev, p.lane.stream))) != FALCON_OK)
+      return st;
+    if (hipEventSynchronize(p.ev) != hipSuccess) return FALCON_ERR_DEVICE;  // M-D2H received
+    if ((st = read_cs(p, j)) != FALCON_OK || (st = issue_placement(p, j, offset)) != FALCON_OK ||
+        (st = dev_err(hipEventRecord(p.ev, p.lane.stream))) != FALCON_OK)
+      return st;
+    offset += p.cs;
+    p.state = kPPend;
+  }
+  for (auto& p : ctx->pipe) {
+    if (p.state != kPPend) continue;
+    if (hipEventSynchronize(p.ev) != hipSuccess) return FALCON_ERR_DEVICE;
+    finish_placement(p, j);
+    p.state = kIdle;
+  }
+  *total = offset;
+  return FALCON_OK;
+}
+
+// Pre-Allocation Scheduler (Sec. 3.1, Fig. 5a): every batch copies its whole
+// worst-case output region (sizes and bound-sized payload area) into a
+// fixed slot of a pinned host buffer, in any order; a merge step then packs
+// the slots into the stream.
+falcon_status compress_pre_allocation(falcon_ctx* ctx, const CompressJob& j, uint64_t* total) {
+  const int ns = (int)ctx->pipe.size();
+  const size_t slot = 32 + j.bc * (4 + max_chunk_bytes(j.dt));
+  const size_t need = slot * j.nbatch;
+  if (need > ctx->pre_cap) {
+    if (ctx->pre_buf) (void)hipHostFree(ctx->pre_buf);
+    ctx->pre_buf = nullptr;
+    ctx->pre_cap = 0;
+    if (hipHostMalloc(&ctx->pre_buf, need, hipHostMallocDefault) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
+    ctx->pre_cap = need;
+  }
+  std::vector<uint64_t> batch_of(ns, 0);
+  uint64_t next = 0, done = 0;
+  falcon_status st;
+  for (auto& p : ctx->pipe) p.state = kIdle;
+  while (done < j.nbatch) {
+    bool moved = false;
+    for (int i = 0; i < ns; ++i) {
+      PipeLane& p = ctx->pipe[i];
+      if (p.state == kIdle) {
+        if (next >= j.nbatch) continue;
+        const uint64_t b = next++;
+        if ((st = issue_batch(ctx, p, j, b, false)) != FALCON_OK) return st;
+        const size_t region = 32 + p.nchunks * (4 + max_chunk_bytes(j.dt));
+        if (
+            (st = dev_err(hipMemcpyAsync(ctx->pre_buf + b * slot, p.g_out, region, hipMemcpyDeviceToHost,
+                                         p.lane.stream))) != FALCON_OK ||
+            (st = dev_err(hipEventRecord(p.ev, p.lane.stream))) != FALCON_OK)
+          return st;
+        batch_of[i] = b;
+        p.state = kBusy;
+        moved = true;
+      } else {
+        const int r = poll(p);
+        if (r < 0) return FALCON_ERR_DEVICE;
+        if (r == 0) continue;
+        ++done;
+        p.state = kIdle;
+        moved = true;
+      }
+    }
+    if (!moved) std::this_thread::yield();
+  }
+  // merge
+  uint64_t offset = 0;
+  for (uint64_t b = 0; b < j.nbatch; ++b) {
+    const uint8_t* sl = ctx->pre_buf + b * slot;
+    const uint64_t c0 = b * j.bc, nb = j.nc - c0 < j.bc ? j.nc - c0 : j.bc;
+    const uint64_t cs = rd64(sl + 24);
+    if (cs > nb * max_chunk_bytes(j.dt)) return FALCON_ERR_DEVICE;
+    memcpy(j.out + 32 + 4 * c0, sl + 32, 4 * nb);
+    memcpy(j.out + j.payload_base + offset, sl + 32 + 4 * nb, cs);
+    offset += cs;
+  }
+  *total = offset;
+  return FALCON_OK;
+}
+
+}  // namespace
 
 falcon_status falcon_compress_host(falcon_ctx* ctx, const void* h_in, size_t n, falcon_dtype dt, void* h_out,
                                    size_t out_cap, size_t* out_len) {
@@ -145,90 +358,39 @@ falcon_status falcon_compress_host(falcon_ctx* ctx, const void* h_in, size_t n, 
     return FALCON_OK;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
-  const bool in_pinned = is_pinned(h_in), out_pinned = is_pinned(h_out);
-  falcon_status st = pipe_ensure(ctx, !(in_pinned && out_pinned));
+  CompressJob j;
+  j.in = static_cast<const uint8_t*>(h_in);
+  j.out = out;
+  j.n = n;
+  j.nc = nc;
+  j.bc = ctx->pipe_batch_chunks;
+  j.nbatch = (nc + j.bc - 1) / j.bc;
+  j.payload_base = 32 + 4 * nc;
+  j.dt = dt;
+  j.es = es;
+  j.in_pinned = is_pinned(h_in);
+  j.out_pinned = is_pinned(h_out);
+  falcon_status st = pipe_ensure(ctx, !(j.in_pinned && j.out_pinned));
   if (st != FALCON_OK) return st;
-  const uint8_t* in = static_cast<const uint8_t*>(h_in);
-  const uint64_t bc = ctx->pipe_batch_chunks;
-  const uint64_t nbatch = (nc + bc - 1) / bc;
-  const uint64_t payload_base = 32 + 4 * nc;
-  const int ns = (int)ctx->pipe.size();
-  // Lanes in launch order: a lane waiting for its batch's byte count may
-  // place its payload only after every batch launched before it.
-  std::vector<int> order(nbatch);
-  uint64_t next = 0, placed = 0, done = 0, offset = 0;
-  for (auto& p : ctx->pipe) p.state = kIdle;
-  while (done < nbatch) {
-    bool moved = false;
-    for (int i = 0; i < ns; ++i) {
-      PipeLane& p = ctx->pipe[i];
-      hipStream_t s = p.lane.stream;
-      if (p.state == kIdle) {
-        if (next >= nbatch) continue;
-        const uint64_t b = next++;
-        p.c0 = b * bc;
-        p.nchunks = nc - p.c0 < bc ? nc - p.c0 : bc;
-        const uint64_t v0 = p.c0 * kChunkN;
-        p.nvals = n - v0 < p.nchunks * kChunkN ? n - v0 : p.nchunks * kChunkN;
-        const uint8_t* src = in + v0 * es;
-        if (!in_pinned) {
-          memcpy(p.p_in, src, p.nvals * es);
-          src = p.p_in;
-        }
-        if ((st = dev_err(hipMemcpyAsync(p.g_in, src, p.nvals * es, hipMemcpyHostToDevice, s))) != FALCON_OK ||
-            (st = enqueue_compress(ctx, p.lane, p.g_in, p.nvals, dt, p.g_out, s, false)) != FALCON_OK ||
-            (st = dev_err(hipMemcpyAsync(p.lane.stage + 40, p.g_out + 24, 8, hipMemcpyDeviceToHost, s))) !=
-                FALCON_OK ||
-            (st = dev_err(hipEventRecord(p.ev, s))) != FALCON_OK)
-          goto fail;
-        order[b] = i;
-        p.state = kMPend;
-        moved = true;
-      } else if (p.state == kMPend) {
-        if (order[placed] != i) continue;  // not the current lane yet
-        const int r = poll(p);
-        if (r < 0) { st = FALCON_ERR_DEVICE; goto fail; }
-        if (r == 0) continue;
-        p.cs = rd64(p.lane.stage + 40);
-        if (p.cs > p.nchunks * max_chunk_bytes(dt)) { st = FALCON_ERR_DEVICE; goto fail; }
-        p.dst = offset;
-        const uint8_t* sizes = p.g_out + 32;
-        if (out_pinned) {
-          if ((st = dev_err(hipMemcpyAsync(out + 32 + 4 * p.c0, sizes, 4 * p.nchunks, hipMemcpyDeviceToHost, s))) !=
-                  FALCON_OK ||
-              (st = dev_err(hipMemcpyAsync(out + payload_base + offset, sizes + 4 * p.nchunks, p.cs,
-                                           hipMemcpyDeviceToHost, s))) != FALCON_OK)
-            goto fail;
-        } else if ((st = dev_err(hipMemcpyAsync(p.p_out, sizes, 4 * p.nchunks + p.cs, hipMemcpyDeviceToHost, s))) !=
-                   FALCON_OK) {
-          goto fail;
-        }
-        if ((st = dev_err(hipEventRecord(p.ev, s))) != FALCON_OK) goto fail;
-        offset += p.cs;
-        ++placed;
-        p.state = kPPend;
-        moved = true;
-      } else {  // kPPend
-        const int r = poll(p);
-        if (r < 0) { st = FALCON_ERR_DEVICE; goto fail; }
-        if (r == 0) continue;
-        if (!out_pinned) {
-          memcpy(out + 32 + 4 * p.c0, p.p_out, 4 * p.nchunks);
-          memcpy(out + payload_base + p.dst, p.p_out + 4 * p.nchunks, p.cs);
-        }
-        ++done;
-        p.state = kIdle;
-        moved = true;
-      }
-    }
-    if (!moved) std::this_thread::yield();
+  uint64_t total = 0;
+  if (ctx->pipe_scheduler == FALCON_SCHED_SYNC_BASED) st = compress_sync_based(ctx, j, &total);
+  else if (ctx->pipe_scheduler == FALCON_SCHED_PRE_ALLOCATION) st = compress_pre_allocation(ctx, j, &total);
+  else st = compress_event_driven(ctx, j, &total);
+  if (st != FALCON_OK) {
+    drain(ctx);
+    return st;
   }
-  write_header(out, dt, n, offset);
-  *out_len = payload_base + offset;
+  write_header(out, dt, n, total);
+  *out_len = j.payload_base + total;
   return FALCON_OK;
-fail:
-  drain(ctx);
-  return st;
+}
+
+falcon_status falcon_set_pipeline_scheduler(falcon_ctx* ctx, falcon_scheduler kind) {
+  if (!ctx || (kind != FALCON_SCHED_EVENT_DRIVEN && kind != FALCON_SCHED_SYNC_BASED &&
+               kind != FALCON_SCHED_PRE_ALLOCATION))
+    return FALCON_ERR_INVALID_ARG;
+  ctx->pipe_scheduler = (int)kind;
+  return FALCON_OK;
 }
 
 falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t in_len, void* h_out,

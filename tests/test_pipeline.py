@@ -1,11 +1,12 @@
-"""Host -> host pipeline (Alg. 1 event-driven scheduler on HIP streams).
+"""Host -> host pipeline (Sec. 3.1: Alg. 1's event-driven scheduler, and the
+Sync-Based and Pre-Allocation schedulers it is compared with, on HIP streams).
 
 The pipeline's stream must be byte-identical to the oracle's and to the
-device-resident call's for every geometry (streams, batch size), with
-pinned and pageable buffers, and decompression through the pipeline must
-give back every bit.  Batches of 1 or 3 chunks over tens of chunks make many
-batches complete out of launch order, which is what the placement order of
-Alg. 1 has to get right.
+device-resident call's for every scheduler and geometry (streams, batch
+size), with pinned and pageable buffers, and decompression through the
+pipeline must give back every bit.  Batches of 1 or 3 chunks over tens of
+chunks make many batches complete out of launch order, which is what the
+placement order of Alg. 1 has to get right.
 """
 import sys
 
@@ -53,10 +54,12 @@ def _inputs():
 
 @pytest.mark.parametrize("streams,batch", [(1, 4096), (3, 1), (4, 3), (4, 1024), (16, 2), (16, 4096)])
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
-def test_pipeline_matches_oracle_and_device(codec, orc, streams, batch, pinned):
+@pytest.mark.parametrize("sched", ["event", "sync", "prealloc"])
+def test_pipeline_matches_oracle_and_device(codec, orc, streams, batch, pinned, sched):
     codec.set_pipeline(streams, batch)
+    codec.set_scheduler(sched)
     for name, x in _inputs():
-        _log(f"[pipeline] {name} n={x.size} streams={streams} batch={batch} pinned={pinned}")
+        _log(f"[pipeline] {name} n={x.size} streams={streams} batch={batch} pinned={pinned} sched={sched}")
         want = orc.compress(x)
         s = codec.compress_host(_host(x, pinned))
         assert s.is_pinned() == pinned
@@ -71,6 +74,11 @@ def test_pipeline_matches_oracle_and_device(codec, orc, streams, batch, pinned):
 def test_pipeline_empty_and_small_buffers(codec, orc):
     from paper_2511_04140_amd import codec as C
     codec.set_pipeline(4, 2)
+    codec.set_scheduler("event")
+    with pytest.raises(KeyError):
+        codec.set_scheduler("round-robin")
+    from paper_2511_04140_amd.codec import lib
+    assert lib().falcon_set_pipeline_scheduler(codec._ctx, 3) == C.ERR_INVALID_ARG
     x = np.zeros(0, np.float32)
     s = codec.compress_host(torch.from_numpy(x))
     assert s.numpy().tobytes() == orc.compress(x)
@@ -116,17 +124,20 @@ def test_pipeline_rejects_corrupt_streams(codec, orc):
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
 def test_pipeline_full_size_sensor_f64(codec, pinned):
     """The 2 GiB float64 workload host -> host with the default geometry
-    (4 streams, 1024-chunk batches): the stream equals the device-resident
-    one and decompresses to the input."""
+    (4 streams, 1024-chunk batches): the stream of every scheduler equals the
+    device-resident one and decompresses to the input."""
     from paper_2511_04140_amd import workloads as W
     codec.set_pipeline()
     x = W.sensor_f64(1 << 28, seed=2)
-    _log(f"[pipeline] full-size sensor_f64 pinned={pinned}")
     xh = _host(x, pinned)
-    s = codec.compress_host(xh)
     dev = codec.compress(xh.cuda())
-    assert s.numel() == dev.numel()
-    assert torch.equal(s.cuda(), dev)
+    for sched in ("event", "sync", "prealloc"):
+        _log(f"[pipeline] full-size sensor_f64 pinned={pinned} sched={sched}")
+        codec.set_scheduler(sched)
+        s = codec.compress_host(xh)
+        assert s.numel() == dev.numel()
+        assert torch.equal(s.cuda(), dev), sched
+    codec.set_scheduler("event")
     del dev
     y = codec.decompress_host(s)
     assert torch.equal(y.view(torch.uint8), xh.view(torch.uint8))
