@@ -74,13 +74,45 @@ void falcon_destroy(falcon_ctx* ctx);
 size_t falcon_compress_bound(size_t n, falcon_dtype dt);
 
 /* Compresses n values at d_in (device) into d_out (device, out_cap bytes).
- * Sec. 3.2-3.5 and Alg. 3: per-chunk integer conversion, adaptive bit-plane
- * encoding, chunk sizes synchronised by a decoupled look-back prefix sum and
- * chunks written at their offsets.  *out_len (host) receives the stream
+ * Sec. 3.2-3.5 and Alg. 3: per-chunk integer conversion and adaptive
+ * bit-plane encoding; the chunk sizes (Sec. 3.4) come from a first pass over
+ * the input, a prefix sum turns them into offsets, and a second pass writes
+ * every chunk at its offset.  *out_len (host) receives the stream
  * length.  Returns FALCON_ERR_BUFFER_TOO_SMALL without launching anything if
  * out_cap < falcon_compress_bound(n, dt).  n = 0 gives a 32-byte stream. */
 falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt,
                               void* d_out, size_t out_cap, size_t* out_len, void* stream);
+
+/* Ablation variants of Sec. 5.4.2 (Fig. 12b).  Each changes one step of
+ * compression and keeps the stream layout:
+ *  ELF    Alg. 2 stops at the first alpha where v (x) 10^alpha is an exact
+ *         integer (the trial-and-error test of Sec. 1) instead of the error
+ *         bound of Thm. 4; loop limits, the recover check and exceptions are
+ *         unchanged, so the stream stays lossless but alpha can come out too
+ *         large (1.11 gets 3).
+ *  SPARSE every bit-plane row is written sparse (16-byte bitmap + non-zero
+ *         bytes), whatever its zero count.
+ *  DENSE  every bit-plane row is written dense (128 bytes). */
+typedef enum falcon_variant {
+  FALCON_VARIANT_FALCON = 0,
+  FALCON_VARIANT_ELF = 1,
+  FALCON_VARIANT_SPARSE = 2,
+  FALCON_VARIANT_DENSE = 3
+} falcon_variant;
+
+/* falcon_compress_bound for a variant.  SPARSE rows can take 144 bytes, so
+ * its chunks reach 11 + 8 + 64 * 144 (f64) and 7 + 4 + 32 * 144 (f32); the
+ * others equal falcon_compress_bound.  0 for an unknown dtype or variant. */
+size_t falcon_compress_bound_variant(size_t n, falcon_dtype dt, falcon_variant v);
+
+/* falcon_compress under variant v (arguments, errors and the stream header
+ * as there; out_cap is checked against falcon_compress_bound_variant).
+ * FALCON_VARIANT_FALCON is falcon_compress.  falcon_decompress reads ELF
+ * and DENSE streams; a SPARSE stream decodes only if every chunk stays
+ * within the f64/f32 chunk bound of falcon_compress_bound, otherwise it is
+ * reported as FALCON_ERR_CORRUPT_STREAM. */
+falcon_status falcon_compress_variant(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt, falcon_variant v,
+                                      void* d_out, size_t out_cap, size_t* out_len, void* stream);
 
 /* Decompresses the stream of in_len bytes at d_in (device) into d_out
  * (device, out_cap_bytes bytes).  Sec. 4: scan of the size array into chunk

@@ -39,6 +39,20 @@
 #define DT_F64 2
 
 #define CHUNK_N 1025 /* Sec. 5.1.4: 1025 values per chunk; n = 64k + 1 (Sec. 3.3) */
+
+/* Variants of the ablation study (Sec. 5.4.2, Fig. 12b).  Only the step named
+ * changes; every variant writes a stream of the same layout, which the one
+ * decoder reads.
+ *   V_FALCON  the method as described;
+ *   V_ELF     Alg. 2 with the trial-and-error stopping test of Sec. 1 (the
+ *             scaled value must be an exact integer) in place of the error
+ *             bound of Thm. 4 (reading R22);
+ *   V_SPARSE  every bit-plane row written sparse (reading R23);
+ *   V_DENSE   every bit-plane row written dense. */
+#define V_FALCON 0
+#define V_ELF 1
+#define V_SPARSE 2
+#define V_DENSE 3
 #define HDR_BYTES 32
 
 /* ------------------------------------------------------------------------- */
@@ -126,7 +140,7 @@ static int fl10_32(float a) {
  * exception is reported as (A_MAX+1, B_MAX+1) (reading R7). */
 typedef struct { int alpha, beta, exc; } dpds_t;
 
-static dpds_t dpds_f64(double v) {
+static dpds_t dpds_f64(double v, int elf) {
   dpds_t res;
   uint64_t b = bits64(v);
   /* Special case of Alg. 2: v = 0.  Sec. 2.1 defines v = 0 as "all 64 bits
@@ -144,7 +158,9 @@ static dpds_t dpds_f64(double v) {
     double r = rint(x);                    /* round (ties-to-even, R5) */
     double eps = fabs(x - r);
     double mu = fabs(x) * 0x1p-52;         /* |v (x) 10^alpha| * 2^-52 */
-    if (eps <= mu) {                       /* Thm. 4 stopping rule */
+    /* Thm. 4 stopping rule; Fal_Elf stops only where the product is an
+     * exact integer (x equal to its floor, Sec. 1) */
+    if (elf ? x == floor(x) : eps <= mu) {
       double back = r / pow10_64(alpha);   /* correctly rounded divide */
       if (bits64(back) != b) break;        /* recover check fails -> exception */
       res.alpha = alpha; res.beta = beta; res.exc = 0;
@@ -157,7 +173,7 @@ static dpds_t dpds_f64(double v) {
   return res;
 }
 
-static dpds_t dpds_f32(float v) {
+static dpds_t dpds_f32(float v, int elf) {
   dpds_t res;
   uint32_t b = bits32(v);
   if (b == 0) { res.alpha = 0; res.beta = 0; res.exc = 0; return res; }
@@ -172,7 +188,7 @@ static dpds_t dpds_f32(float v) {
     float r = rintf(x);
     float eps = fabsf(x - r);
     float mu = fabsf(x) * 0x1p-23f;
-    if (eps <= mu) {
+    if (elf ? x == floorf(x) : eps <= mu) {
       float back = r / pow10_32(alpha);
       if (bits32(back) != b) break;
       res.alpha = alpha; res.beta = beta; res.exc = 0;
@@ -190,11 +206,11 @@ static dpds_t dpds_f32(float v) {
 /* ------------------------------------------------------------------------- */
 /* Computes the chunk header bytes (A, B) and Z = {z_1..z_n} for n values.
  * z is returned as uint64 (for binary32 only the low 32 bits are used). */
-static void transform_f64(const double* v, int n, int* A, int* B, uint64_t* z) {
+static void transform_f64(const double* v, int n, int elf, int* A, int* B, uint64_t* z) {
   int any_exc = 0, amax = 0;
   double vmax = 0.0;
   for (int i = 0; i < n; ++i) {
-    dpds_t d = dpds_f64(v[i]);
+    dpds_t d = dpds_f64(v[i], elf);
     if (d.exc) any_exc = 1;
     else if (d.alpha > amax) amax = d.alpha;
     if (!d.exc && fabs(v[i]) > vmax) vmax = fabs(v[i]);
@@ -221,11 +237,11 @@ static void transform_f64(const double* v, int n, int* A, int* B, uint64_t* z) {
   }
 }
 
-static void transform_f32(const float* v, int n, int* A, int* B, uint64_t* z) {
+static void transform_f32(const float* v, int n, int elf, int* A, int* B, uint64_t* z) {
   int any_exc = 0, amax = 0;
   float vmax = 0.0f;
   for (int i = 0; i < n; ++i) {
-    dpds_t d = dpds_f32(v[i]);
+    dpds_t d = dpds_f32(v[i], elf);
     if (d.exc) any_exc = 1;
     else if (d.alpha > amax) amax = d.alpha;
     if (!d.exc && fabsf(v[i]) > vmax) vmax = fabsf(v[i]);
@@ -259,9 +275,10 @@ static void transform_f32(const float* v, int n, int* A, int* B, uint64_t* z) {
 static int zbit(uint64_t z, int p) { return (int)((z >> p) & 1u); }
 
 /* Encodes one chunk whose Z has n = 64k+1 entries.  W = 64 or 32 is the
- * integer width, zb = 8 or 4 the number of bytes of z_1.  Returns the byte
- * count written to out (out must hold the worst case). */
-static size_t encode_chunk_z(const uint64_t* z, int n, int W, int zb, int A, int B,
+ * integer width, zb = 8 or 4 the number of bytes of z_1; variant V_SPARSE or
+ * V_DENSE fixes every row's scheme.  Returns the byte count written to out
+ * (out must hold the worst case). */
+static size_t encode_chunk_z(const uint64_t* z, int n, int W, int zb, int A, int B, int variant,
                              uint8_t* out) {
   const int m = n - 1;          /* entries of M: z_2..z_n */
   const int rowb = m / 8;       /* bytes per row of M^T */
@@ -295,6 +312,8 @@ static size_t encode_chunk_z(const uint64_t* z, int n, int W, int zb, int A, int
     for (int b = 0; b < rowb; ++b) if (row[b] == 0) lambda++;
     /* Sparse iff lambda > (n-1)/64 (Sec. 3.3); the tie goes to Dense (R9, R10). */
     int dense = !(lambda > bmb);
+    if (variant == V_SPARSE) dense = 0;
+    if (variant == V_DENSE) dense = 1;
     if (dense) {
       /* Flag bits: big-endian bit string, right-aligned, row r at bit (w - r),
        * '1' = dense (R14). */
@@ -387,33 +406,44 @@ static int untransform_f32(const uint64_t* z, int n, int A, int B, float* v) {
 /* ------------------------------------------------------------------------- */
 static int dtype_bytes(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 0); }
 static size_t chunk_bound(int dt) { return dt == DT_F64 ? 11 + 8 + 64 * 128 : 7 + 4 + 32 * 128; }
-
-size_t orc_bound(size_t n, int dt) {
-  size_t nc = (n + CHUNK_N - 1) / CHUNK_N;
-  return HDR_BYTES + nc * (4 + chunk_bound(dt));
+/* An all-sparse row can take 16 bitmap bytes + 128 data bytes. */
+static size_t chunk_bound_v(int dt, int variant) {
+  if (variant != V_SPARSE) return chunk_bound(dt);
+  return dt == DT_F64 ? 11 + 8 + 64 * 144 : 7 + 4 + 32 * 144;
 }
+
+size_t orc_bound_v(size_t n, int dt, int variant) {
+  size_t nc = (n + CHUNK_N - 1) / CHUNK_N;
+  return HDR_BYTES + nc * (4 + chunk_bound_v(dt, variant));
+}
+size_t orc_bound(size_t n, int dt) { return orc_bound_v(n, dt, V_FALCON); }
 
 int orc_fl10_f64(double a) { init_tables(); return fl10_64(a); }
 int orc_fl10_f32(float a) { init_tables(); return fl10_32(a); }
 
 void orc_dpds_f64(double v, int* alpha, int* beta, int* exc) {
   init_tables();
-  dpds_t d = dpds_f64(v);
+  dpds_t d = dpds_f64(v, 0);
   *alpha = d.alpha; *beta = d.beta; *exc = d.exc;
 }
 void orc_dpds_f32(float v, int* alpha, int* beta, int* exc) {
   init_tables();
-  dpds_t d = dpds_f32(v);
+  dpds_t d = dpds_f32(v, 0);
   *alpha = d.alpha; *beta = d.beta; *exc = d.exc;
 }
 
-/* Alg. 2 over an array (batch form of the two functions above, for tests). */
-void orc_dpds_many(const void* v, size_t n, int dt, int* alpha, int* beta, int* exc) {
+/* Alg. 2 over an array (batch form of the two functions above, for tests);
+ * variant V_ELF uses the trial-and-error stopping test. */
+void orc_dpds_many_v(const void* v, size_t n, int dt, int variant, int* alpha, int* beta, int* exc) {
   init_tables();
+  const int elf = variant == V_ELF;
   for (size_t i = 0; i < n; ++i) {
-    dpds_t d = dt == DT_F64 ? dpds_f64(((const double*)v)[i]) : dpds_f32(((const float*)v)[i]);
+    dpds_t d = dt == DT_F64 ? dpds_f64(((const double*)v)[i], elf) : dpds_f32(((const float*)v)[i], elf);
     alpha[i] = d.alpha; beta[i] = d.beta; exc[i] = d.exc;
   }
+}
+void orc_dpds_many(const void* v, size_t n, int dt, int* alpha, int* beta, int* exc) {
+  orc_dpds_many_v(v, n, dt, V_FALCON, alpha, beta, exc);
 }
 void orc_fl10_many(const void* v, size_t n, int dt, int* out) {
   init_tables();
@@ -432,24 +462,26 @@ static void pad_f32(const float* v, size_t nv, int chunk_n, float* buf) {
 
 /* Encodes one chunk of nv (1 <= nv <= chunk_n) values with chunk length
  * chunk_n = 64k+1 (k >= 1).  Used for the full stream and for small-n tests. */
-int orc_encode_chunk(const void* vals, size_t nv, int dt, int chunk_n, uint8_t* out,
-                     size_t* out_len) {
+int orc_encode_chunk_v(const void* vals, size_t nv, int dt, int chunk_n, int variant, uint8_t* out,
+                       size_t* out_len) {
   init_tables();
   if (chunk_n < 65 || (chunk_n - 1) % 64 != 0 || nv == 0 || nv > (size_t)chunk_n)
     return ORC_ERR_ARG;
+  if (variant < V_FALCON || variant > V_DENSE) return ORC_ERR_ARG;
+  const int elf = variant == V_ELF;
   uint64_t* z = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)chunk_n);
   int A = 0, B = 0;
   if (dt == DT_F64) {
     double* buf = (double*)malloc(sizeof(double) * (size_t)chunk_n);
     pad_f64((const double*)vals, nv, chunk_n, buf);
-    transform_f64(buf, chunk_n, &A, &B, z);
-    *out_len = encode_chunk_z(z, chunk_n, 64, 8, A, B, out);
+    transform_f64(buf, chunk_n, elf, &A, &B, z);
+    *out_len = encode_chunk_z(z, chunk_n, 64, 8, A, B, variant, out);
     free(buf);
   } else if (dt == DT_F32) {
     float* buf = (float*)malloc(sizeof(float) * (size_t)chunk_n);
     pad_f32((const float*)vals, nv, chunk_n, buf);
-    transform_f32(buf, chunk_n, &A, &B, z);
-    *out_len = encode_chunk_z(z, chunk_n, 32, 4, A, B, out);
+    transform_f32(buf, chunk_n, elf, &A, &B, z);
+    *out_len = encode_chunk_z(z, chunk_n, 32, 4, A, B, variant, out);
     free(buf);
   } else {
     free(z);
@@ -457,6 +489,9 @@ int orc_encode_chunk(const void* vals, size_t nv, int dt, int chunk_n, uint8_t* 
   }
   free(z);
   return ORC_OK;
+}
+int orc_encode_chunk(const void* vals, size_t nv, int dt, int chunk_n, uint8_t* out, size_t* out_len) {
+  return orc_encode_chunk_v(vals, nv, dt, chunk_n, V_FALCON, out, out_len);
 }
 
 /* Decodes one chunk payload of len bytes into chunk_n values. */
@@ -507,11 +542,11 @@ static uint64_t get_u64(const uint8_t* p) { uint64_t v = 0; for (int k = 0; k < 
 /* Whole-array compression into the container format.  Chunks are independent
  * (Sec. 3, Alg. 3); their sizes are prefix-summed into offsets (Sec. 3.4)
  * and the payloads written back to back. */
-int orc_compress(const void* in, size_t n, int dt, uint8_t* out, size_t cap, size_t* out_len) {
+int orc_compress_v(const void* in, size_t n, int dt, int variant, uint8_t* out, size_t cap, size_t* out_len) {
   init_tables();
   int s = dtype_bytes(dt);
-  if (s == 0) return ORC_ERR_ARG;
-  if (cap < orc_bound(n, dt)) { *out_len = orc_bound(n, dt); return ORC_ERR_SMALL; }
+  if (s == 0 || variant < V_FALCON || variant > V_DENSE) return ORC_ERR_ARG;
+  if (cap < orc_bound_v(n, dt, variant)) { *out_len = orc_bound_v(n, dt, variant); return ORC_ERR_SMALL; }
   size_t nc = (n + CHUNK_N - 1) / CHUNK_N;
   uint8_t* sizes = out + HDR_BYTES;
   uint8_t* pay = sizes + 4 * nc;
@@ -520,8 +555,8 @@ int orc_compress(const void* in, size_t n, int dt, uint8_t* out, size_t cap, siz
     size_t nv = n - c * CHUNK_N;
     if (nv > CHUNK_N) nv = CHUNK_N;
     size_t len = 0;
-    int st = orc_encode_chunk((const uint8_t*)in + c * CHUNK_N * (size_t)s, nv, dt, CHUNK_N,
-                              pay + off, &len);
+    int st = orc_encode_chunk_v((const uint8_t*)in + c * CHUNK_N * (size_t)s, nv, dt, CHUNK_N, variant,
+                                pay + off, &len);
     if (st != ORC_OK) return st;
     put_u32(sizes + 4 * c, (uint32_t)len);
     off += len;
@@ -537,6 +572,9 @@ int orc_compress(const void* in, size_t n, int dt, uint8_t* out, size_t cap, siz
   put_u64(out + 24, (uint64_t)off);
   *out_len = HDR_BYTES + 4 * nc + off;
   return ORC_OK;
+}
+int orc_compress(const void* in, size_t n, int dt, uint8_t* out, size_t cap, size_t* out_len) {
+  return orc_compress_v(in, n, dt, V_FALCON, out, cap, out_len);
 }
 
 /* Parses and checks the container header; fills n, dt, nc, payload bytes. */

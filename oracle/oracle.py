@@ -14,6 +14,8 @@ DT_F32 = 1
 DT_F64 = 2
 CHUNK_N = 1025
 OK, ERR_ARG, ERR_SMALL, ERR_CORRUPT = 0, 1, 2, 3
+# ablation variants of Sec. 5.4.2 (Fig. 12b)
+VARIANTS = {"falcon": 0, "elf": 1, "sparse": 2, "dense": 3}
 
 _lib = None
 
@@ -50,6 +52,14 @@ def lib():
         L.orc_stream_info.argtypes = [vp, sz, ctypes.POINTER(sz), ip]
         L.orc_stream_info.restype = ctypes.c_int
         L.orc_dpds_many.argtypes = [vp, sz, ctypes.c_int, vp, vp, vp]
+        L.orc_dpds_many_v.argtypes = [vp, sz, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.orc_bound_v.argtypes = [sz, ctypes.c_int, ctypes.c_int]
+        L.orc_bound_v.restype = sz
+        L.orc_compress_v.argtypes = [vp, sz, ctypes.c_int, ctypes.c_int, vp, sz, ctypes.POINTER(sz)]
+        L.orc_compress_v.restype = ctypes.c_int
+        L.orc_encode_chunk_v.argtypes = [vp, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                         ctypes.POINTER(sz)]
+        L.orc_encode_chunk_v.restype = ctypes.c_int
         L.orc_fl10_many.argtypes = [vp, sz, ctypes.c_int, vp]
         _lib = L
     return _lib
@@ -83,12 +93,13 @@ def dpds(v, dtype=np.float64):
     return a.value, b.value, bool(e.value)
 
 
-def dpds_many(x: np.ndarray):
-    """Alg. 2 over an array: returns (alpha, beta, exception) arrays."""
+def dpds_many(x: np.ndarray, variant: str = "falcon"):
+    """Alg. 2 over an array: returns (alpha, beta, exception) arrays.
+    variant "elf" uses the trial-and-error stopping test of Sec. 1."""
     x = np.ascontiguousarray(x)
     n = x.size
     a = np.empty(n, np.int32); b = np.empty(n, np.int32); e = np.empty(n, np.int32)
-    lib().orc_dpds_many(_ptr(x), n, _dt(x), _ptr(a), _ptr(b), _ptr(e))
+    lib().orc_dpds_many_v(_ptr(x), n, _dt(x), VARIANTS[variant], _ptr(a), _ptr(b), _ptr(e))
     return a, b, e.astype(bool)
 
 
@@ -99,17 +110,19 @@ def fl10_many(x: np.ndarray) -> np.ndarray:
     return out
 
 
-def bound(n, dtype):
-    return lib().orc_bound(n, DT_F64 if np.dtype(dtype) == np.float64 else DT_F32)
+def bound(n, dtype, variant: str = "falcon"):
+    return lib().orc_bound_v(n, DT_F64 if np.dtype(dtype) == np.float64 else DT_F32, VARIANTS[variant])
 
 
-def compress(x: np.ndarray) -> bytes:
+def compress(x: np.ndarray, variant: str = "falcon") -> bytes:
+    """The stream of x; variant names an ablation of Sec. 5.4.2."""
     x = np.ascontiguousarray(x)
     dt = _dt(x)
-    cap = lib().orc_bound(x.size, dt)
+    v = VARIANTS[variant]
+    cap = lib().orc_bound_v(x.size, dt, v)
     out = np.empty(cap, np.uint8)
     n = ctypes.c_size_t()
-    st = lib().orc_compress(_ptr(x), x.size, dt, _ptr(out), cap, ctypes.byref(n))
+    st = lib().orc_compress_v(_ptr(x), x.size, dt, v, _ptr(out), cap, ctypes.byref(n))
     if st != OK:
         raise RuntimeError(f"oracle compress failed: {st}")
     return out[: n.value].tobytes()
@@ -141,12 +154,13 @@ def validate(stream: bytes) -> int:
     return lib().orc_validate(_ptr(buf), buf.size)
 
 
-def encode_chunk(vals: np.ndarray, chunk_n: int = CHUNK_N) -> bytes:
+def encode_chunk(vals: np.ndarray, chunk_n: int = CHUNK_N, variant: str = "falcon") -> bytes:
     vals = np.ascontiguousarray(vals)
     dt = _dt(vals)
-    out = np.empty(11 + 8 + 64 * (chunk_n - 1) // 8 + 64, np.uint8)
+    out = np.empty(11 + 8 + 64 * ((chunk_n - 1) // 8 + (chunk_n - 1) // 64) + 64, np.uint8)
     n = ctypes.c_size_t()
-    st = lib().orc_encode_chunk(_ptr(vals), vals.size, dt, chunk_n, _ptr(out), ctypes.byref(n))
+    st = lib().orc_encode_chunk_v(_ptr(vals), vals.size, dt, chunk_n, VARIANTS[variant], _ptr(out),
+                                  ctypes.byref(n))
     if st != OK:
         raise ValueError(f"oracle encode_chunk failed: {st}")
     return out[: n.value].tobytes()

@@ -65,6 +65,8 @@ OP_DECOMPRESS = 1
 PLAN_TUNE = 1
 PLAN_GRAPH = 2
 SCHEDULERS = {"event": 0, "sync": 1, "prealloc": 2}
+# ablation variants of compression (Sec. 5.4.2)
+VARIANTS = {"falcon": 0, "elf": 1, "sparse": 2, "dense": 3}
 
 
 def _load():
@@ -81,6 +83,10 @@ def _load():
     L.falcon_compress_bound.argtypes = [sz, i]
     L.falcon_compress_bound.restype = sz
     L.falcon_compress.argtypes = [vp, vp, sz, i, vp, sz, ctypes.POINTER(sz), vp]
+    L.falcon_compress_bound_variant.argtypes = [sz, i, i]
+    L.falcon_compress_bound_variant.restype = sz
+    L.falcon_compress_variant.argtypes = [vp, vp, sz, i, i, vp, sz, ctypes.POINTER(sz), vp]
+    L.falcon_compress_variant.restype = i
     L.falcon_compress.restype = i
     L.falcon_decompress.argtypes = [vp, vp, sz, vp, sz, ctypes.POINTER(sz), vp]
     L.falcon_decompress.restype = i
@@ -211,6 +217,25 @@ class Codec:
                                    _stream_handle(x.device))
         if st != 0:
             raise FalconError(st, "falcon_compress")
+        return out[: olen.value]
+
+    def compress_variant(self, x: torch.Tensor, variant: str, out: torch.Tensor | None = None) -> torch.Tensor:
+        """compress() under an ablation variant: "falcon", "elf" (Elf's
+        decimal places), "sparse" (every row sparse) or "dense"."""
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("compress needs a contiguous device tensor")
+        code = _dtype_code(x.dtype)
+        v = VARIANTS[variant]
+        n = x.numel()
+        cap = lib().falcon_compress_bound_variant(n, code, v)
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        olen = ctypes.c_size_t()
+        st = lib().falcon_compress_variant(self._ctx, ctypes.c_void_p(x.data_ptr() if n else 0), n, code, v,
+                                           ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(olen),
+                                           _stream_handle(x.device))
+        if st != 0:
+            raise FalconError(st, "falcon_compress_variant")
         return out[: olen.value]
 
     def decompress(self, stream: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -93,7 +93,7 @@ int grid_for(int max_grid, uint64_t nchunks, int waves_per_block) {
 // Two-pass compression: size pass, scan of the sizes, write pass (see
 // codec_kernels.hpp).  The lane's offset array receives the scan.
 falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
-                               hipStream_t s, bool timed) {
+                               hipStream_t s, bool timed, int variant) {
   const uint64_t nc = chunks_of(n);
   falcon_status st = prepare_launch(l, nc ? nc : 1, scan_tiles(nc) + 1, s);
   if (st == FALCON_OK) st = grow_raw(&l.meta, &l.meta_cap, nc ? nc : 1, s);
@@ -113,22 +113,24 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.gsizes = l.gsizes;
   a.offsets = l.offsets;
   a.relative = 0;
-  const int g1 = grid_for(max_grid_c(ctx, dt, 1, kCompressWaves), nc, kCompressWaves);
-  const int g2 = grid_for(max_grid_c(ctx, dt, 2, kCompressWaves), nc, kCompressWaves);
+  const int nw = variant ? kVariantWaves : kCompressWaves;
+  const int g1 = grid_for(variant ? ctx->grid_v[dt][variant][1] : max_grid_c(ctx, dt, 1, nw), nc, nw);
+  const int g2 = grid_for(variant ? ctx->grid_v[dt][variant][2] : max_grid_c(ctx, dt, 2, nw), nc, nw);
+  auto launch = [&](int pass, int grid) {
+    a.total_waves = (uint32_t)(grid * nw);
+    return dev_err(variant ? launch_compress_variant(a, (int)dt, variant, pass, grid, s)
+                           : launch_compress(a, (int)dt, pass, nw, grid, s));
+  };
   auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
   if (timed) ctx->timed = false;
   if ((st = mark(0)) != FALCON_OK) return st;
-  if (nc) {
-    a.total_waves = (uint32_t)(g1 * kCompressWaves);
-    if ((st = dev_err(launch_compress(a, (int)dt, 1, kCompressWaves, g1, s))) != FALCON_OK) return st;
-  }
+  if (nc && (st = launch(1, g1)) != FALCON_OK) return st;
   if ((st = mark(1)) != FALCON_OK) return st;
   if (nc && (st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch, s))) !=
                 FALCON_OK)
     return st;
   if ((st = mark(2)) != FALCON_OK) return st;
-  a.total_waves = (uint32_t)(g2 * kCompressWaves);
-  if ((st = dev_err(launch_compress(a, (int)dt, 2, kCompressWaves, g2, s))) != FALCON_OK) return st;
+  if ((st = launch(2, g2)) != FALCON_OK) return st;
   if ((st = mark(3)) != FALCON_OK) return st;
   if (timed) {
     ctx->timed = true;
@@ -224,6 +226,9 @@ falcon_status falcon_create(int device, falcon_ctx** out) {
     }
     ctx->grid_d[form] = max_grid_decompress(device, form);
   }
+  for (int form = 1; form <= 2; ++form)
+    for (int v = 1; v <= 3; ++v)
+      for (int pass = 1; pass <= 2; ++pass) ctx->grid_v[form][v][pass] = max_grid_compress_variant(device, form, v, pass);
   *out = ctx;
   return FALCON_OK;
 }
@@ -253,17 +258,31 @@ falcon_status falcon_stream_info(const void* h_hdr, size_t len, size_t* n, falco
 
 falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt, void* d_out,
                               size_t out_cap, size_t* out_len, void* stream) {
+  return falcon_compress_variant(ctx, d_in, n, dt, FALCON_VARIANT_FALCON, d_out, out_cap, out_len, stream);
+}
+
+size_t falcon_compress_bound_variant(size_t n, falcon_dtype dt, falcon_variant v) {
+  if (v < FALCON_VARIANT_FALCON || v > FALCON_VARIANT_DENSE) return 0;
+  if (v != FALCON_VARIANT_SPARSE) return falcon_compress_bound(n, dt);
+  const size_t per = dt == FALCON_FLOAT64 ? 11 + 8 + 64 * 144 : dt == FALCON_FLOAT32 ? 7 + 4 + 32 * 144 : 0;
+  if (per == 0) return 0;
+  return 32 + chunks_of(n) * (4 + per);
+}
+
+falcon_status falcon_compress_variant(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt, falcon_variant v,
+                                      void* d_out, size_t out_cap, size_t* out_len, void* stream) {
   if (!ctx || !d_out || !out_len || (n && !d_in)) return FALCON_ERR_INVALID_ARG;
+  if (v < FALCON_VARIANT_FALCON || v > FALCON_VARIANT_DENSE) return FALCON_ERR_INVALID_ARG;
   const size_t es = elem_size(dt);
   if (es == 0) return FALCON_ERR_INVALID_ARG;
   if (((uintptr_t)d_in % es) || ((uintptr_t)d_out % 4)) return FALCON_ERR_INVALID_ARG;
-  if (out_cap < falcon_compress_bound(n, dt)) return FALCON_ERR_BUFFER_TOO_SMALL;
+  if (out_cap < falcon_compress_bound_variant(n, dt, v)) return FALCON_ERR_BUFFER_TOO_SMALL;
   const uint64_t nc = chunks_of(n);
   if (nc >= 0xFFFFFFF0ull) return FALCON_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
   Lane& l = ctx->main;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : l.stream;
-  falcon_status st = enqueue_compress(ctx, l, d_in, n, dt, d_out, s, true);
+  falcon_status st = enqueue_compress(ctx, l, d_in, n, dt, d_out, s, true, (int)v);
   if (st != FALCON_OK) return st;
   if ((st = dev_err(hipMemcpyAsync(l.stage + 40, static_cast<uint8_t*>(d_out) + 24, 8, hipMemcpyDeviceToHost, s))) !=
       FALCON_OK)

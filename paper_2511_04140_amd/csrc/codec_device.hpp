@@ -61,10 +61,10 @@ struct __attribute__((aligned(16))) LdsTables {
   double p64[48];
   float p32[24];
 };
-template <int NW>
+template <int NW, int WB = kWaveLds / 16>
 struct __attribute__((aligned(16))) BlockLdsT {
   LdsTables tab;
-  uint4 wave[NW][kWaveLds / 16];
+  uint4 wave[NW][WB];
 };
 
 __device__ __forceinline__ void load_tables(LdsTables& s) {
@@ -288,8 +288,8 @@ __device__ __forceinline__ void xpose16(uint32_t (&a)[16]) {
 }
 
 // Byte access into a wave's LDS buffer.
-template <int NW>
-__device__ __forceinline__ uint8_t* wave_bytes(BlockLdsT<NW>& s, int wid) {
+template <int NW, int WB>
+__device__ __forceinline__ uint8_t* wave_bytes(BlockLdsT<NW, WB>& s, int wid) {
   return reinterpret_cast<uint8_t*>(&s.wave[wid][0]);
 }
 

@@ -39,6 +39,16 @@ __device__ __forceinline__ bool eps_test(typename T::U b, typename T::F P, typen
   return T::abs(x - r) <= T::abs(x) * T::mu_scale();
 }
 
+// The trial-and-error stopping test that Sec. 1 attributes to earlier
+// codecs (the Fal_Elf ablation of Sec. 5.4.2): v (x) 10^alpha must be an
+// exact integer.  Returns the rounded value in r.
+template <class T>
+__device__ __forceinline__ bool exact_test(typename T::U b, typename T::F P, typename T::F& r) {
+  const typename T::F x = T::f(b) * P;
+  r = T::rnd(x);
+  return x == r;
+}
+
 // Stopping test plus the recover check of Alg. 2: round(v (x) 10^a) / 10^a
 // must give back v bit for bit.
 template <class T>
@@ -61,7 +71,7 @@ __device__ __forceinline__ void set_bit(uint32_t& m, bool c, int k) {
 // the lanes in lock-step over alpha.  Used only when the fast decision below
 // cannot settle the chunk.  Returns true if some value is an exception;
 // otherwise amax gets the lane's largest decimal place.
-template <class T>
+template <class T, bool ELF = false>
 __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename T::U (&vb)[17], int& amax) {
   bool exc = false;
   amax = 0;
@@ -79,7 +89,7 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
         } else {
           const typename T::F P = T::pow10(sm, a);
           typename T::F r;
-          if (eps_test<T>(v, P, r)) {
+          if (ELF ? exact_test<T>(v, P, r) : eps_test<T>(v, P, r)) {
             done = true;
             if (T::u(r / P) != v) exc = true;
             else amax = max(amax, a);
@@ -222,6 +232,57 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
   }
   A = wave_max_i32(amax);
   A = (int)uniform((uint32_t)A);
+  B = A + maxfl + 1;
+  case1 = B <= T::BMAX;
+}
+
+// Ablation variants of Sec. 5.4.2 (Fig. 12b).  Each changes one step and
+// keeps the stream layout.
+enum : int {
+  kVarFalcon = 0,  // the method as described
+  kVarElf = 1,     // Alg. 2 with exact_test in place of the bound of Thm. 4
+  kVarSparse = 2,  // every bit-plane row sparse
+  kVarDense = 3    // every bit-plane row dense
+};
+// Per-wave LDS buffer of the variant kernels, in 16-byte blocks: an
+// all-sparse float64 chunk (11 + 8 + 64 * 144 = 9235 bytes) at any 16-byte
+// phase.
+constexpr int kVarWaveBlocks = 580;
+
+// decide_case for kVarElf: the same exceptions and header, with every value
+// run through Alg. 2 under the trial-and-error stopping test (no shortcut:
+// the test is not monotone in alpha, so bisection does not apply).
+template <class T>
+__device__ __forceinline__ void decide_case_elf(const LdsTables& sm, const typename T::U (&vb)[17], int& A, int& B,
+                                                bool& case1) {
+  using U = typename T::U;
+  const U mag_lo = T::u(T::pow10(sm, -T::AMAX));
+  const U mag_hi = T::u(T::pow10(sm, T::BMAX));
+  bool exc = false;
+  U vmax = 0;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    const U m = T::mag(vb[k]);
+    exc |= (vb[k] != 0) && (m < mag_lo || m >= mag_hi);
+    vmax = m > vmax ? m : vmax;
+  }
+  int amax = 0;
+  if (!ballot(exc)) exc = alg2_literal<T, true>(sm, vb, amax);
+  if (ballot(exc)) {
+    A = T::AMAX + 1;
+    B = T::BMAX + 1;
+    case1 = false;
+    return;
+  }
+  vmax = (U)uniform64((uint64_t)wave_max64((uint64_t)vmax));
+  if (vmax == 0) {
+    A = 0;
+    B = 0;
+    case1 = true;
+    return;
+  }
+  const int maxfl = (int)uniform((uint32_t)fl10<T>(sm, vmax));
+  A = (int)uniform((uint32_t)wave_max_i32(amax));
   B = A + maxfl + 1;
   case1 = B <= T::BMAX;
 }
@@ -389,11 +450,12 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
 }
 
 // a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
-template <class T, bool TRANSPOSE = true>
+template <class T, bool TRANSPOSE = true, int V = kVarFalcon>
 __device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
                                                int lane, ChunkPlanes& cp) {
   bool case1;
-  decide_case<T>(sm, vb, cp.A, cp.B, case1);
+  if constexpr (V == kVarElf) decide_case_elf<T>(sm, vb, cp.A, cp.B, case1);
+  else decide_case<T>(sm, vb, cp.A, cp.B, case1);
   compress_transform<T, TRANSPOSE>(sm, buf, vb, lane, case1, cp);
 }
 
@@ -404,32 +466,12 @@ struct ChunkStats {
   uint32_t S;
 };
 
-template <class T>
-__device__ __forceinline__ ChunkStats chunk_stats(const ChunkPlanes& cp) {
-  const uint32_t w = cp.w;
-  uint64_t flags = 0;
-  uint32_t rows = 0;
-  for_planes_down<T::W - 1>([&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    if (p < (int)w) {
-      const uint32_t fld = plane_field<T, p>(cp.lo, cp.hi);
-      const uint64_t E = ballot((fld & 0xFFu) != 0), O = ballot((fld & 0xFF00u) != 0);
-      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
-      const bool dense = nnz >= 112;
-      flags |= (uint64_t)dense << p;
-      rows += dense ? 128u : 16u + nnz;
-    }
-  });
-  ChunkStats st;
-  st.flags = flags;
-  st.S = 3 + T::ZB + ((w + 7) >> 3) + rows;
-  return st;
-}
-
 // a8-a9 from the byte ORs of the size pass: byte 2L of row p (elements
 // 16L..16L+7, plane p) is non-zero iff bit p of or0 is set; byte 2L+1 the
-// same with or1.  Gives the same flags and size as chunk_stats.
-template <class T>
+// same with or1, so the row's non-zero bytes are counted without the
+// transpose.  The kVarSparse / kVarDense ablations fix every row's scheme
+// instead.
+template <class T, int V = kVarFalcon>
 __device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp) {
   const uint32_t w = cp.w;
   uint64_t flags = 0;
@@ -439,7 +481,7 @@ __device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp) {
     if (p < (int)w) {
       const uint64_t E = ballot(((cp.or0 >> p) & 1) != 0), O = ballot(((cp.or1 >> p) & 1) != 0);
       const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
-      const bool dense = nnz >= 112;
+      const bool dense = V == kVarDense || (V != kVarSparse && nnz >= 112);
       flags |= (uint64_t)dense << p;
       rows += dense ? 128u : 16u + nnz;
     }
@@ -774,16 +816,16 @@ __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
 // vb holds the chunk's values when loaded is set (else they are loaded
 // here); prefetch() runs as soon as vb is free, so that the next chunk's
 // loads overlap the rest of this one.
-template <class T, class Prefetch>
+template <class T, int V, class Prefetch>
 __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
                                            const CompressSeries& sd, uint64_t t, int lane,
                                            typename T::U (&vb)[17], bool loaded, Prefetch&& prefetch) {
   const uint64_t c = t - sd.chunk0;
   if (!loaded) load_chunk<T>(sd, c, lane, vb);
   ChunkPlanes cp;
-  compress_front<T, false>(tab, buf, vb, lane, cp);
+  compress_front<T, false, V>(tab, buf, vb, lane, cp);
   prefetch();
-  const ChunkStats st = chunk_stats_or<T>(cp);
+  const ChunkStats st = chunk_stats_or<T, V>(cp);
   if (lane == 0) {
     ChunkMeta m;
     m.flags = st.flags;
@@ -831,17 +873,20 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   wave_lds_sync();
 }
 
-template <int NW>
-__device__ __forceinline__ void pass_prologue(BlockLdsT<NW>& sm, const CompressArgs& a, bool headers) {
+template <int NW, int WB>
+__device__ __forceinline__ void pass_prologue(BlockLdsT<NW, WB>& sm, const CompressArgs& a, bool headers) {
   load_tables(sm.tab);
   if (headers) empty_series_headers(a);
   __syncthreads();
 }
 
-// PASS 1 = size pass, 2 = write pass; one dtype per launch.
-template <class T, int NW, int PASS>
+// PASS 1 = size pass, 2 = write pass; one dtype per launch.  V selects an
+// ablation variant (size pass only: the write pass follows the flags the
+// size pass stored); WB is the per-wave LDS buffer in 16-byte blocks, which
+// an all-sparse float64 chunk (up to 9235 bytes) needs larger.
+template <class T, int NW, int PASS, int V = kVarFalcon, int WB = kWaveLds / 16>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_pass(CompressArgs a) {
-  __shared__ BlockLdsT<NW> sm;
+  __shared__ BlockLdsT<NW, WB> sm;
   pass_prologue(sm, a, PASS == 2);
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
@@ -864,7 +909,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         load_chunk<T>(sd, tn + a.t0 - sd.chunk0, lane, vb);
       }
     };
-    if (PASS == 1) size_chunk<T>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
+    if (PASS == 1) size_chunk<T, V>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
     else write_chunk<T>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
     if (!more) break;
     t = tn;
@@ -885,11 +930,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     auto none = []() {};
     if (uniform(sd.dtype) == 2) {
       uint64_t vb[17];
-      if (PASS == 1) size_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      if (PASS == 1) size_chunk<TF64, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
       else write_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     } else {
       uint32_t vb[17];
-      if (PASS == 1) size_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      if (PASS == 1) size_chunk<TF32, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
       else write_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     }
   }

@@ -116,6 +116,8 @@ struct falcon_ctx {
   // and workgroup size (8 or 16 waves)
   int grid_c[4][3][2] = {};
   int grid_d[4] = {};
+  // the same for the ablation-variant compression kernels: [form][variant][pass]
+  int grid_v[3][4][3] = {};
   // events of the last timed call: before the first kernel, after it, after
   // the scan, after the last kernel (decompression: the first two coincide)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -141,9 +143,10 @@ namespace falcon_host {
 // Enqueues the compression of n values at d_in into the stream buffer d_out
 // on lane l (stream s).  Nothing is waited for; the stream's payload byte
 // count lands in the stream header at d_out + 24.  With timed, events
-// around the kernel feed falcon_last_kernel_ms.
+// around the kernel feed falcon_last_kernel_ms.  variant != 0 selects an
+// ablation variant's kernels (falcon_variant).
 falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
-                               hipStream_t s, bool timed);
+                               hipStream_t s, bool timed, int variant = 0);
 
 // Enqueues the decompression of a stream at d_in whose header (n, dt,
 // payload) the host already knows and has checked, into d_out, followed by

@@ -111,8 +111,16 @@ uint64_t scan_tiles(uint64_t n);
 // every series' chunk sizes into one array indexed by launch chunk.
 hipError_t launch_batch_dprep(DecompressSeries* many, uint32_t ns, uint64_t total_chunks, uint32_t* sizes_out,
                               Ctl* ctl, uint32_t epoch, hipStream_t s);
+// Compression under an ablation variant of Sec. 5.4.2 (variant 1: Elf's
+// decimal places, 2: every row sparse, 3: every row dense), one dtype per
+// launch (form 1 or 2), kVariantWaves wavefronts per workgroup.
+constexpr int kVariantWaves = 8;
+hipError_t launch_compress_variant(const CompressArgs& a, int form, int variant, int pass, int grid, hipStream_t s);
+const void* compress_variant_kernel_f64(int variant, int pass);
+const void* compress_variant_kernel_f32(int variant, int pass);
 // Largest number of co-resident workgroups of each kernel on the device.
 int max_grid_compress(int device, int form, int pass, int nw);
+int max_grid_compress_variant(int device, int form, int variant, int pass);
 int max_grid_decompress(int device, int form);
 
 }  // namespace falcon_dev

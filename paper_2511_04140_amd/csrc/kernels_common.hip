@@ -149,6 +149,15 @@ hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, in
   return launch_compress_mixed(a, pass, nw, grid, s);
 }
 
+hipError_t launch_compress_variant(const CompressArgs& a, int form, int variant, int pass, int grid, hipStream_t s) {
+  const void* fn = form == 2 ? compress_variant_kernel_f64(variant, pass)
+                             : form == 1 ? compress_variant_kernel_f32(variant, pass) : nullptr;
+  if (!fn) return hipErrorInvalidValue;
+  CompressArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(64 * kVariantWaves), args, 0, s);
+}
+
 hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s) {
   if (form == 2) return launch_decompress_f64(a, grid, s);
   if (form == 1) return launch_decompress_f32(a, grid, s);
@@ -187,6 +196,12 @@ int max_grid_compress(int device, int form, int pass, int nw) {
   const void* fn = form == 2 ? compress_kernel_f64(pass, nw)
                              : form == 1 ? compress_kernel_f32(pass, nw) : compress_kernel_mixed(pass, nw);
   return max_grid_of(fn, device, 64 * nw);
+}
+
+int max_grid_compress_variant(int device, int form, int variant, int pass) {
+  const void* fn = form == 2 ? compress_variant_kernel_f64(variant, pass)
+                             : form == 1 ? compress_variant_kernel_f32(variant, pass) : nullptr;
+  return fn ? max_grid_of(fn, device, 64 * kVariantWaves) : 0;
 }
 
 int max_grid_decompress(int device, int form) {

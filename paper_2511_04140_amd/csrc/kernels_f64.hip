@@ -28,6 +28,22 @@ static const void* kernel_nw(int pass) {
 
 const void* compress_kernel_f64(int pass, int nw) { return nw == 8 ? kernel_nw<8>(pass) : kernel_nw<16>(pass); }
 
+template <int V>
+static const void* size_pass_variant_f64() {
+  return reinterpret_cast<const void*>(&k_compress_pass<TF64, kVariantWaves, 1, V, kVarWaveBlocks>);
+}
+
+// The write pass follows the flags the size pass stored, so one write
+// kernel serves every variant.
+const void* compress_variant_kernel_f64(int variant, int pass) {
+  if (pass == 2)
+    return reinterpret_cast<const void*>(&k_compress_pass<TF64, kVariantWaves, 2, kVarFalcon, kVarWaveBlocks>);
+  if (variant == kVarElf) return size_pass_variant_f64<kVarElf>();
+  if (variant == kVarSparse) return size_pass_variant_f64<kVarSparse>();
+  if (variant == kVarDense) return size_pass_variant_f64<kVarDense>();
+  return nullptr;
+}
+
 const void* decompress_kernel_f64() { return reinterpret_cast<const void*>(&k_decompress<TF64>); }
 
 }  // namespace falcon_dev
