@@ -2,8 +2,9 @@
 
 One step = one pass of the whole path over the workload already resident in
 HBM: compress (integer conversion, delta + zigzag, adaptive bit-plane
-encoding, look-back offsets, stream compaction) followed by decompress
-(offsets, bit-plane decoding, inverse transforms).  Workload: 268,435,456
+encoding sized in a first pass, a prefix sum of the chunk sizes, the chunks
+written at their offsets in a second pass) followed by decompress (offsets,
+bit-plane decoding, inverse transforms).  Workload: 268,435,456
 float64 sensor-like values (2 GiB, 65,536-value segments at 1-6 decimal
 places, 1% full-precision outliers, specials at 1e-5), seeded synthetic.
 
@@ -297,6 +298,56 @@ def codec_bound(x):
     return C.compress_bound(x.size, torch.float64 if x.dtype.itemsize == 8 else torch.float32)
 
 
+def ablation(codec, torch, x_c2, reps=5):
+    """Sec. 5.4.2 (Fig. 12b): Falcon against Fal_Elf (Elf's trial-and-error
+    decimal places), Fal_Sparse and Fal_Dense (one row scheme for every
+    bit plane), device-resident, on the 1 Mi-value walk, the 2 GiB float64
+    workload and the 2 GiB float32 workload.  Per variant: compressed /
+    original bytes, and the median kernel time of compression (size pass,
+    scan, write pass) and of decompression as GB/s of original bytes.  A
+    Fal_Sparse stream whose chunks exceed the format's chunk bound is not
+    decodable by the ordinary decoder (decompress_gbps null)."""
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    res = {}
+    for label, make in (("walk_f64_2^20", lambda: W.walk_f64(1 << 20, seed=1)),
+                        ("sensor_f64_2^28", lambda: x_c2),
+                        ("mixed_f32_2^29", lambda: W.mixed_f32(1 << 29, seed=3))):
+        x = make()
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.empty_like(xd)
+        code = 2 if x.dtype == np.float64 else 1
+        row = {}
+        for variant in ("falcon", "elf", "sparse", "dense"):
+            sbuf = torch.empty(C.lib().falcon_compress_bound_variant(x.size, code, C.VARIANTS[variant]),
+                               dtype=torch.uint8, device="cuda")
+            kc, kd = [], []
+            for _ in range(reps + 1):
+                s = codec.compress_variant(xd, variant, out=sbuf)
+                kc.append(codec.last_kernel_ms())
+            dec = True
+            for _ in range(reps + 1):
+                try:
+                    codec.decompress(s, out=yd)
+                except C.FalconError:
+                    dec = False
+                    break
+                kd.append(codec.last_kernel_ms())
+            if dec:
+                assert torch.equal(yd.view(torch.uint8), xd.view(torch.uint8)), (label, variant)
+            row[variant] = {
+                "ratio": round(s.numel() / x.nbytes, 6),
+                "compress_gbps": round(x.nbytes / (float(np.median(kc[1:])) * 1e-3) / 1e9, 2),
+                "decompress_gbps": round(x.nbytes / (float(np.median(kd[1:])) * 1e-3) / 1e9, 2) if dec else None,
+            }
+            del sbuf, s
+        res[label] = row
+        del xd, yd
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +358,7 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host -> host pipeline measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 10,000-series batched launch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the ablation-variant measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of the input "
                          "(2 GiB read + 2 GiB write) as the reference for HBM byte counters")
@@ -435,6 +487,9 @@ def main():
         out["serving"] = serving(codec, torch)
         torch.cuda.empty_cache()
         log(f"serving: {out['serving']}")
+    if not args.no_ablation:
+        out["ablation"] = ablation(codec, torch, x)
+        log(f"ablation: {out['ablation']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x)
     codec.close()
