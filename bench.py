@@ -348,6 +348,91 @@ def ablation(codec, torch, x_c2, reps=5):
     return res
 
 
+def _device_rates(codec, torch, xd, reps=5):
+    """Median kernel time of compression and of decompression over reps
+    calls on a device-resident tensor; returns (ratio, compress GB/s,
+    decompress GB/s) and checks the round trip."""
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    nbytes = xd.numel() * xd.element_size()
+    sbuf = torch.empty(C.compress_bound(xd.numel(), xd.dtype), dtype=torch.uint8, device=xd.device)
+    yd = torch.empty_like(xd)
+    kc, kd = [], []
+    for _ in range(reps + 1):
+        s = codec.compress(xd, out=sbuf)
+        kc.append(codec.last_kernel_ms())
+        codec.decompress(s, out=yd)
+        kd.append(codec.last_kernel_ms())
+    assert torch.equal(yd.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
+    tc, td = float(np.median(kc[1:])), float(np.median(kd[1:]))
+    return (round(s.numel() / nbytes, 6), round(nbytes / (tc * 1e-3) / 1e9, 2),
+            round(nbytes / (td * 1e-3) / 1e9, 2))
+
+
+def studies(codec, torch):
+    """Parameter studies of Sec. 5.3 on synthetic stand-ins:
+    - beta: the sensor signal (no outliers or specials) rounded to 1..17
+      significant digits, 2^26 values (512 MiB) each, device-resident
+      (Fig. 10);
+    - data size: prefixes of one 8 GiB sensor array from 100 MB to 8 GB,
+      device-resident and host -> host through the pipeline from pinned
+      buffers (Fig. 11);
+    - batch size: the pipeline's batch from 0.5 to 8 x 1025 x 1024 values at
+      4 and 16 streams on the 2 GiB prefix, pinned (the batch-size table)."""
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    log = lambda m: print(f"[studies] {m}", file=sys.stderr, flush=True)
+    res = {"beta": {}, "data_size": {}, "batch": {}}
+    for d in range(1, 18):
+        xd = torch.from_numpy(W.significant_f64(1 << 26, 5, d)).cuda()
+        r, c, dd = _device_rates(codec, torch, xd)
+        res["beta"][d] = {"ratio": r, "compress_gbps": c, "decompress_gbps": dd}
+        log(f"beta {d}: {res['beta'][d]}")
+        del xd
+    big = W.sensor_f64(1 << 30, seed=2)
+    host = torch.from_numpy(big).pin_memory()
+    del big
+    sbuf = torch.empty(C.compress_bound(host.numel(), torch.float64), dtype=torch.uint8, pin_memory=True)
+    ybuf = torch.empty(host.numel(), dtype=torch.float64, pin_memory=True)
+
+    def host_rates(n, reps=3):
+        tc = td = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            s = codec.compress_host(host[:n], out=sbuf)
+            t1 = time.perf_counter()
+            y = codec.decompress_host(s, out=ybuf[:n])
+            t2 = time.perf_counter()
+            tc, td = min(tc, t1 - t0), min(td, t2 - t1)
+        assert torch.equal(y.view(torch.uint8), host[:n].view(torch.uint8)), "host round trip failed"
+        return round(8 * n / tc / 1e9, 2), round(8 * n / td / 1e9, 2)
+
+    codec.set_pipeline()
+    for mb in (100, 250, 500, 1000, 2000, 4000, 8000):
+        n = min(host.numel(), mb * 10 ** 6 // 8)
+        xd = host[:n].cuda()
+        r, c, dd = _device_rates(codec, torch, xd)
+        del xd
+        torch.cuda.empty_cache()
+        hc, hd = host_rates(n)
+        res["data_size"][f"{8 * n / 1e9:.2f} GB"] = {
+            "ratio": r, "device_compress_gbps": c, "device_decompress_gbps": dd,
+            "host_compress_gbps": hc, "host_decompress_gbps": hd}
+        log(f"size {mb} MB: {res['data_size'][f'{8 * n / 1e9:.2f} GB']}")
+    n2 = 1 << 28
+    for ns in (4, 16):
+        for bc in (512, 1024, 2048, 4096, 8192):
+            codec.set_pipeline(ns, bc)
+            hc, hd = host_rates(n2)
+            res["batch"][f"{ns}x{bc}"] = {"n_streams": ns, "batch_values": bc * 1025,
+                                          "host_compress_gbps": hc, "host_decompress_gbps": hd}
+            log(f"batch {ns}x{bc}: {res['batch'][f'{ns}x{bc}']}")
+    codec.set_pipeline()
+    del host, sbuf, ybuf
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +444,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 10,000-series batched launch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the ablation-variant measurement")
+    ap.add_argument("--studies", action="store_true",
+                    help="also run the parameter studies (beta, data size, pipeline batch size)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of the input "
                          "(2 GiB read + 2 GiB write) as the reference for HBM byte counters")
@@ -490,6 +577,9 @@ def main():
     if not args.no_ablation:
         out["ablation"] = ablation(codec, torch, x)
         log(f"ablation: {out['ablation']}")
+    if args.studies:
+        out["studies"] = studies(codec, torch)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x)
     codec.close()

@@ -58,7 +58,7 @@ def _pool():
 
 
 def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
-               special_rate: float = 1e-5, block_segments: int = 16) -> np.ndarray:
+               special_rate: float = 1e-5, block_segments: int = 16, rounded: bool = True) -> np.ndarray:
     """Sensor-like float64 series in 65,536-value segments.
 
     Each segment keeps d ~ U{1..6} decimal places; values are
@@ -68,7 +68,8 @@ def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
     special_rate is replaced by a special value (NaN with payload, +-Inf,
     -0.0, subnormal).  Blocks of block_segments segments draw from their own
     generator seeded with (seed, block), so the result does not depend on
-    the number of threads.
+    the number of threads.  rounded=False keeps the signal unrounded (and
+    without outliers or specials).
     """
     out = np.empty(n, np.float64)
     step = block_segments * SEGMENT
@@ -86,6 +87,9 @@ def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
         m = hi - lo
         rng = np.random.default_rng([seed, b, 1])
         x = 100.0 * _SIN_1E4[np.arange(lo, hi) % 10000] + (out[lo:hi] + offset)
+        if not rounded:
+            out[lo:hi] = x
+            return
         nseg = (m + SEGMENT - 1) // SEGMENT
         scale = np.repeat(_POW10[rng.integers(1, 7, nseg)], SEGMENT)[:m]
         v = np.rint(x * scale) / scale + 0.0
@@ -100,6 +104,19 @@ def sensor_f64(n: int = 1 << 28, seed: int = 2, outlier_rate: float = 0.01,
         offsets = np.concatenate([[0.0], np.cumsum(totals)[:-1]]) if blocks else []
         list(ex.map(finish, blocks, offsets))
     return out
+
+
+def significant_f64(n: int, seed: int, digits: int) -> np.ndarray:
+    """The unrounded sensor signal rounded to `digits` significant decimal
+    digits: rint(x * 10^j) / 10^j with j = digits - 1 - floor(log10 |x|)
+    (the nearest double to that decimal for digits <= 15)."""
+    x = sensor_f64(n, seed, rounded=False)
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log10(np.abs(x)))
+    e[~np.isfinite(e)] = 0.0
+    j = digits - 1 - e
+    p = 10.0 ** np.abs(j)
+    return np.where(j >= 0, np.rint(x * p) / p, np.rint(x / p) * p) + 0.0
 
 
 def _field_f32(rng_seed, count: int, side: int = 512, lattice: int = 17, ex=None) -> np.ndarray:
