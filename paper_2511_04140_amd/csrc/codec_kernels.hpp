@@ -68,10 +68,11 @@ __device__ __forceinline__ void set_bit(uint32_t& m, bool c, int k) {
 }
 
 // Literal Alg. 2 over the 17 values of this lane, one slot at a time with
-// the lanes in lock-step over alpha.  Used only when the fast decision below
-// cannot settle the chunk.  Returns true if some value is an exception;
+// the lanes in lock-step over alpha; with ELF, under the trial-and-error
+// stopping test (the Fal_Elf ablation, whose test is not monotone in alpha
+// and so admits no bisection).  Returns true if some value is an exception;
 // otherwise amax gets the lane's largest decimal place.
-template <class T, bool ELF = false>
+template <class T, bool ELF>
 __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename T::U (&vb)[17], int& amax) {
   bool exc = false;
   amax = 0;
@@ -106,23 +107,30 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
 // header bytes A (alpha_max) and B (beta_hat_max), and whether Case 1 holds.
 //
 // The paper evaluates Alg. 2 value by value.  Here the wave decides the
-// chunk with the same outcome in fewer steps:
+// chunk with the same outcome in fewer steps.  The fact used throughout: a
+// value that is not an exception passes both the stopping test and the
+// recover check at every scale s from its decimal place alpha_i up to its
+// limit lim_i = min(AMAX, BMAX-1-FL10(|v|)) (Thm. 2, Thm. 4: v * 10^s is
+// then an integer below 10^BMAX, rounded back exactly, and the division
+// returns the double nearest v's shortest string), and fails the stopping
+// test below alpha_i (Alg. 2 stops at the first pass).
 //  1. A value is an exception outright if it is -0.0, subnormal, Inf or NaN
 //     or has FL10 >= BMAX or FL10 <= -(AMAX+1); with magnitudes ordered as
 //     integers that is |v| < fl(10^-AMAX) or |v| >= fl(10^BMAX) (v != +0).
-//  2. Otherwise let L* = min(AMAX, BMAX-1-FL10(v_max)), the largest scale at
-//     which beta_hat stays within BMAX.  Every value passing the stopping
-//     test and the recover check at L* has alpha_i <= L* (Thm. 2-4: its
-//     shortest string has at most BMAX digits and at most L* places), and
-//     the stopping test holds from alpha_i up to L* and fails below it, so
-//     alpha_max is found by bisection over [0, L*].  The recover check is
-//     repeated at the final alpha_max.
+//  2. Otherwise let L* = min(AMAX, BMAX-1-FL10(v_max)) <= every lim_i, the
+//     largest scale at which beta_hat stays within BMAX.  If every value
+//     passes the stopping test at L*, alpha_max is the least scale in
+//     [0, L*] at which all pass, found by bisection, and the recover check
+//     is applied there once.
 //  3. A value failing at L* is an exception if L* is its own limit, or if it
-//     fails again at its own limit: a non-exception value passes both tests
-//     at every scale between its decimal place and its limit (the rounding
-//     error of v * 10^s stays within one unit in the last place).
-//  4. Anything else (no exception found, alpha_max > L*, i.e. Case 2 with a
-//     real header) runs the literal Alg. 2.
+//     fails the full test at its own limit.
+//  4. If no failing value is an exception, alpha_max lies in (L*, max lim_i]
+//     (so the chunk is Case 2 with a real header): it is the least a at
+//     which every value passes the stopping test at min(a, lim_i), found by
+//     bisection, and the recover check is applied there once.
+// When no value is an exception both bisections are exact and the recover
+// checks pass; so a failed recover check means some value is one, and the
+// chunk gets the exception header, as Alg. 2 would give it.
 template <class T>
 __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename T::U (&vb)[17], int& A, int& B,
                             bool& case1) {
@@ -162,7 +170,6 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
       set_bit(fail, !eps_test<T>(vb[k], P, r), k);
     }
   }
-  bool literal = false;
   if (ballot(fail != 0) == 0) {
     int lo = 0, hi = lstar;
     while (lo < hi) {
@@ -177,20 +184,24 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
       if (ballot(bad)) lo = mid + 1;
       else hi = mid;
     }
+    bool bad = false;
     {
       const F P = T::pow10(sm, hi);
-      bool bad = false;
 #pragma unroll
       for (int k = 0; k < 17; ++k) bad |= !full_test<T>(vb[k], P);
-      literal = ballot(bad) != 0;
     }
-    if (!literal) {
-      A = hi;
-      B = hi + maxfl + 1;
-      case1 = true;
+    if (ballot(bad)) {
+      A = T::AMAX + 1;
+      B = T::BMAX + 1;
+      case1 = false;
       return;
     }
-  } else {
+    A = hi;
+    B = hi + maxfl + 1;
+    case1 = true;
+    return;
+  }
+  {
     // A failing value whose own limit equals L* is an exception.  Its limit
     // min(AMAX, BMAX - 1 - FL10(|v|)) equals L* exactly when L* = AMAX or
     // FL10(|v|) = FL10(v_max), i.e. |v| >= fl(10^FL10(v_max)): one compare,
@@ -219,20 +230,40 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
       case1 = false;
       return;
     }
-    literal = true;
   }
-  // literal Alg. 2 for the whole chunk
-  int amax;
-  const bool lexc = alg2_literal<T>(sm, vb, amax);
-  if (ballot(lexc)) {
+  // step 4: bisection over (L*, max lim_i] with value k tested at
+  // min(a, lim_k); +0.0 passes at every scale
+  int lim[17];
+  int lmax = lstar;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    lim[k] = vb[k] == 0 ? T::AMAX : min(T::AMAX, T::BMAX - 1 - fl10<T>(sm, T::mag(vb[k])));
+    lmax = max(lmax, lim[k]);
+  }
+  lmax = (int)uniform((uint32_t)wave_max_i32(lmax));
+  int lo = lstar + 1, hi = lmax;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+      F r;
+      bad |= !eps_test<T>(vb[k], T::pow10(sm, min(mid, lim[k])), r);
+    }
+    if (ballot(bad)) lo = mid + 1;
+    else hi = mid;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) bad |= !full_test<T>(vb[k], T::pow10(sm, min(hi, lim[k])));
+  if (ballot(bad)) {
     A = T::AMAX + 1;
     B = T::BMAX + 1;
     case1 = false;
     return;
   }
-  A = wave_max_i32(amax);
-  A = (int)uniform((uint32_t)A);
-  B = A + maxfl + 1;
+  A = hi;
+  B = hi + maxfl + 1;
   case1 = B <= T::BMAX;
 }
 

@@ -93,6 +93,11 @@ for d in range(0, 16):
     SMALL_CASES.append((f"decimal{d}_f64",
                         lambda W, rng, d=d: W.decimal_f64(7 * 1025 + 100, seed=100 + d, places=d,
                                                           magnitude=10.0 ** (12 - min(d, 12)))))
+for d in (12, 14, 15, 16):
+    # mixed magnitudes at high precision: chunks whose small values need more
+    # places than L* allows (the bisection above L*)
+    SMALL_CASES.append((f"significant{d}_f64",
+                        lambda W, rng, d=d: W.significant_f64(30 * 1025 + 77, seed=300 + d, digits=d)))
 for d in range(0, 8):
     SMALL_CASES.append((f"decimal{d}_f32",
                         lambda W, rng, d=d: W.decimal_f32(7 * 1025 + 100, seed=200 + d, places=d,
