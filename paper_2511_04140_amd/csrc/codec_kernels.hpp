@@ -684,6 +684,12 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   using S_ = typename T::S;
   int lane = lane_in;  // opaque, see compress_front
   asm volatile("" : "+v"(lane));
+  // the chunk's size, phase and span are wave-uniform; in scalar registers
+  // they keep the row cursor below scalar too
+  S = uniform(S);
+  pad = uniform(pad);
+  total = uniform(total);
+  bad = uniform((uint32_t)bad) != 0;
   if (bad) {
     if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -700,11 +706,16 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   if (w > (uint32_t)T::W) bad = true;
   const uint32_t nflag = (w + 7) >> 3;
   if (3 + T::ZB + nflag > S) bad = true;
+  // bad, flags and the row cursor below are wave-uniform; saying so keeps
+  // the per-row scheme branch and the cursor in scalar registers (a
+  // divergent-looking branch would cost exec-mask bookkeeping per row)
+  bad = uniform((uint32_t)bad) != 0;
   uint64_t flags = 0;
   if (!bad) {
     for (uint32_t f = 0; f < nflag; ++f)
       flags = (flags << 8) | (uint32_t)__builtin_amdgcn_readlane((int)hb, 3 + T::ZB + (int)f);
   }
+  flags = uniform64(flags);
   // d2: rows -> bit-plane fields of this lane (row bytes 2L, 2L+1).  The
   // row cursor and the error flag are wave-uniform; reads use clamped
   // addresses so that a corrupt stream never reads outside the buffer (its
@@ -720,25 +731,27 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
     constexpr int p = decltype(pc)::value;
     if (p < (int)w) {
       uint32_t fld;
-      if ((flags >> p) & 1) {
-        ubad |= cur + 128 > total;
+      const bool dense = (flags >> p) & 1;
+      uint32_t nnz = 0;  // sparse rows: non-zero bytes after the bitmap
+      if (dense) {
         const uint32_t a0 = min(cur + 2 * (uint32_t)lane, kLim - 1);
         fld = (uint32_t)buf[a0] | ((uint32_t)buf[a0 + 1] << 8);
-        cur += 128;
       } else {
-        ubad |= cur + 16 > total;
         // bitmap byte L/4 covers this lane's row bytes 2L and 2L+1 (MSB first)
         const uint32_t bm = buf[min(cur + ((uint32_t)lane >> 2), kLim)];
         const uint32_t nz0 = (bm >> (sh + 1)) & 1u, nz1 = (bm >> sh) & 1u;
         const uint64_t E = ballot(nz0 != 0), O = ballot(nz1 != 0);
-        const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
+        nnz = (uint32_t)(__popcll(E) + __popcll(O));
         const uint32_t rank = mbcnt(E) + mbcnt(O);
         const uint32_t d0 = cur + 16 + rank;
         const uint32_t r0 = buf[min(d0, kLim)], r1 = buf[min(d0 + nz0, kLim)];
         fld = (nz0 ? r0 : 0u) | ((nz1 ? r1 : 0u) << 8);
-        ubad |= cur + 16 + nnz > total;
-        cur += 16 + nnz;
       }
+      // the row's extent, checked and stepped over after the join so that
+      // the cursor stays one scalar value
+      const uint32_t row = dense ? 128u : 16u + nnz;
+      ubad |= cur + row > total;
+      cur += row;
       plane_put<p>(lo, hi, fld);
     }
   });
@@ -920,7 +933,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ BlockLdsT<NW, WB> sm;
   pass_prologue(sm, a, PASS == 2);
   const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
+  const int wid = (int)uniform(threadIdx.x >> 6);  // wave-uniform: keeps the chunk loop scalar
   uint8_t* buf = wave_bytes(sm, wid);
   typename T::U vb[17];
   if (PASS == 2 && a.total_chunks == 0 && !a.many && blockIdx.x == 0 && wid == 0)
@@ -953,7 +966,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ BlockLdsT<NW> sm;
   pass_prologue(sm, a, PASS == 2);
   const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
+  const int wid = (int)uniform(threadIdx.x >> 6);  // wave-uniform: keeps the chunk loop scalar
   uint8_t* buf = wave_bytes(sm, wid);
   for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
     const uint64_t tg = t + a.t0;
@@ -1007,7 +1020,7 @@ __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4)
   load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
+  const int wid = (int)uniform(threadIdx.x >> 6);  // wave-uniform: keeps the chunk loop scalar
   uint8_t* buf = wave_bytes(sm, wid);
   decompress_loop(a, buf, lane, wid,
                   [&](const DecompressSeries& sd, uint64_t c, uint32_t S, uint32_t pad, uint32_t total, bool bad) {

@@ -11,7 +11,7 @@ __global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4)
   load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
+  const int wid = (int)uniform(threadIdx.x >> 6);  // wave-uniform: keeps the chunk loop scalar
   uint8_t* buf = wave_bytes(sm, wid);
   decompress_loop(a, buf, lane, wid,
                   [&](const DecompressSeries& sd, uint64_t c, uint32_t S, uint32_t pad, uint32_t total, bool bad) {
