@@ -67,6 +67,34 @@ struct __attribute__((aligned(16))) BlockLdsT {
   uint4 wave[NW][WB];
 };
 
+// Global-memory views of generic pointers.  An access through a generic
+// pointer compiles to a flat instruction, which counts against the LDS
+// counter as well as the vector-memory counter, so every wait for an LDS
+// access would also wait for outstanding HBM loads (such as the prefetch of
+// the next chunk).  Accesses through these views compile to global
+// instructions, which count against the vector-memory counter only.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ global_ptr<T> gbl(T* p) {
+  return (global_ptr<T>)p;
+}
+// 16-byte global load and store (a builtin vector type, which can be read and
+// written through an address-space-qualified pointer).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gload16(const void* p) {
+  const u32x4 v = *gbl(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore16(void* p, const uint4& v) {
+  u32x4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *gbl(reinterpret_cast<u32x4*>(p)) = w;
+}
+
 __device__ __forceinline__ void load_tables(LdsTables& s) {
   for (int i = threadIdx.x; i < 45; i += blockDim.x) s.p64[i] = c_pow10_f64[i];
   for (int i = threadIdx.x; i < 21; i += blockDim.x) s.p32[i] = c_pow10_f32[i];

@@ -354,7 +354,7 @@ __device__ __forceinline__ void write_stream_header(uint8_t* out, uint32_t dtype
       case 6: w = (uint32_t)payload; break;
       default: w = (uint32_t)(payload >> 32); break;
     }
-    reinterpret_cast<uint32_t*>(out)[lane] = w;
+    gbl(reinterpret_cast<uint32_t*>(out))[lane] = w;
   }
 }
 
@@ -368,7 +368,7 @@ template <class T>
 __device__ __forceinline__ void load_chunk(const CompressSeries& sd, uint64_t c, int lane,
                                            typename T::U (&vb)[17]) {
   using U = typename T::U;
-  const U* in = reinterpret_cast<const U*>(sd.in);
+  const global_ptr<const U> in = gbl(reinterpret_cast<const U*>(sd.in));
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
   const uint32_t nv = rem < (uint64_t)kChunk ? (uint32_t)rem : (uint32_t)kChunk;
@@ -579,10 +579,10 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dal, u
   for (uint32_t k = lane; k < nblk; k += 64) {
     const uint32_t b_lo = 16 * k, b_hi = b_lo + 16;
     if (b_lo >= ph && b_hi <= end) {
-      *reinterpret_cast<uint4*>(dal + b_lo) = *reinterpret_cast<const uint4*>(buf + b_lo);
+      gstore16(dal + b_lo, *reinterpret_cast<const uint4*>(buf + b_lo));
     } else {
       const uint32_t from = b_lo > ph ? b_lo : ph, to = b_hi < end ? b_hi : end;
-      for (uint32_t b = from; b < to; ++b) dal[b] = buf[b];
+      for (uint32_t b = from; b < to; ++b) gbl(dal)[b] = buf[b];
     }
   }
 }
@@ -612,9 +612,10 @@ struct Staged {
 // Block i of a staged span: whole, or byte by byte where it would pass the
 // end of the readable bytes.
 __device__ __forceinline__ uint4 load_block(const uint8_t* sal, uint64_t avail, uint32_t i) {
-  if (16ull * i + 16 <= avail) return *reinterpret_cast<const uint4*>(sal + 16 * i);
+  if (16ull * i + 16 <= avail) return gload16(sal + 16 * i);
   uint32_t wv[4] = {0, 0, 0, 0};
-  for (uint32_t b = 0; b < 16 && 16ull * i + b < avail; ++b) wv[b >> 2] |= (uint32_t)sal[16 * i + b] << (8 * (b & 3));
+  for (uint32_t b = 0; b < 16 && 16ull * i + b < avail; ++b)
+    wv[b >> 2] |= (uint32_t)gbl(sal)[16 * i + b] << (8 * (b & 3));
   return make_uint4(wv[0], wv[1], wv[2], wv[3]);
 }
 
@@ -637,9 +638,9 @@ __device__ __forceinline__ Staged stage_issue(const DecompressSeries& sd, uint64
   const uint32_t lo = f64 ? (uint32_t)TF64::ZB + 3 : (uint32_t)TF32::ZB + 3;
   const uint32_t hi = f64 ? (uint32_t)TF64::BOUND : (uint32_t)TF32::BOUND;
   const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
-  st.S = uniform(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes)[c]);
-  const uint64_t base = relative ? uniform64(offsets[sd.chunk0]) : 0;
-  const uint64_t off = uniform64(offsets[t]) - base;
+  st.S = uniform(gbl(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes))[c]);
+  const uint64_t base = relative ? uniform64(gbl(offsets)[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(gbl(offsets)[t]) - base;
   st.bad = st.S > hi || st.S < lo || off + st.S > sd.payload_bytes ||
            (c == nc - 1 && off + st.S != sd.payload_bytes);
   st.pad = 0;
@@ -805,7 +806,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
   const int nv = rem < (uint64_t)kChunk ? (int)rem : (int)kChunk;
-  U* out = reinterpret_cast<U*>(sd.out) + base;
+  const global_ptr<U> out = gbl(reinterpret_cast<U*>(sd.out) + base);
   constexpr uint32_t kLine = 128 / sizeof(U);
   const int mis = (int)(((uintptr_t)out / sizeof(U)) % kLine);
 #pragma unroll
@@ -821,14 +822,29 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
 // ---------------------------------------------------------------------------
 template <class Series>
 __device__ __forceinline__ Series find_series(const Series& one, const Series* many, uint32_t ns, uint64_t t) {
-  if (!many) return one;  // one-series launch: the descriptor travels in the arguments
+  if (!many) {  // one-series launch: the descriptor travels in the arguments
+    Series s = one;
+    // keeps the compiler from merging this copy with the global load below
+    // into one load through a generic pointer (a flat access)
+    asm volatile("" ::: "memory");
+    return s;
+  }
   uint32_t lo = 0, hi = ns - 1;  // last series with chunk0 <= t
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
-    if (many[mid].chunk0 <= t) lo = mid;
+    if (gbl(many)[mid].chunk0 <= t) lo = mid;
     else hi = mid - 1;
   }
-  return many[lo];
+  // the descriptor as 8-byte global loads (a struct copy through an
+  // address-space-qualified pointer is not available in C++)
+  static_assert(sizeof(Series) % 8 == 0, "descriptor made of 8-byte words");
+  uint64_t w[sizeof(Series) / 8];
+  const global_ptr<const uint64_t> q = gbl(reinterpret_cast<const uint64_t*>(many + lo));
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(Series) / 8; ++i) w[i] = q[i];
+  Series s;
+  __builtin_memcpy(&s, w, sizeof(Series));
+  return s;
 }
 
 // Writes the 32-byte header of every empty series of a batch launch and its
@@ -840,7 +856,7 @@ __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
   for (uint32_t i = threadIdx.x; i < a.nseries; i += blockDim.x) {
     const CompressSeries& sd = a.many[i];
     if (sd.n != 0) continue;
-    uint32_t* o = reinterpret_cast<uint32_t*>(sd.out);
+    const global_ptr<uint32_t> o = gbl(reinterpret_cast<uint32_t*>(sd.out));
     o[0] = 0x4E434C46u;  // "FLCN"
     o[1] = 1u | (sd.dtype << 8);
     o[2] = (uint32_t)kChunk;
@@ -880,7 +896,7 @@ __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, c
     m.pad = 0;
     a.meta[t] = m;
     a.gsizes[t] = st.S;
-    reinterpret_cast<uint32_t*>(sd.out + kHdrBytes)[c] = st.S;
+    gbl(reinterpret_cast<uint32_t*>(sd.out + kHdrBytes))[c] = st.S;
   }
   wave_lds_sync();
 }
@@ -892,7 +908,7 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   const uint64_t c = t - sd.chunk0;
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
   if (!loaded) load_chunk<T>(sd, c, lane, vb);
-  const uint64_t* mp = reinterpret_cast<const uint64_t*>(a.meta + t);
+  const global_ptr<const uint64_t> mp = gbl(reinterpret_cast<const uint64_t*>(a.meta + t));
   const uint64_t flags = uniform64(mp[0]);
   const uint64_t m1 = uniform64(mp[1]);
   const uint32_t S = (uint32_t)m1;
@@ -903,8 +919,8 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   prefetch();
   // the payload goes to dst; it is assembled at dst's 16-byte phase so that
   // the copy moves whole aligned blocks
-  const uint64_t base = a.relative ? uniform64(a.offsets[sd.chunk0]) : 0;
-  const uint64_t off = uniform64(a.offsets[t]) - base;
+  const uint64_t base = a.relative ? uniform64(gbl(a.offsets)[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(gbl(a.offsets)[t]) - base;
   uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
   assemble_payload<T>(buf + ph, cp, flags, S, lane);
