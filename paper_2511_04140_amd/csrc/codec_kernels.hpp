@@ -568,11 +568,22 @@ __device__ __forceinline__ void assemble_payload(uint8_t* buf, const ChunkPlanes
   });
 }
 
+// One piece of a partial block: n = 1, 2, 4 or 8 bytes at an offset that
+// is a multiple of n, from LDS to global memory.
+__device__ __forceinline__ void copy_piece(const uint8_t* src, uint8_t* dst, uint32_t o, uint32_t n) {
+  if (n == 8) *gbl(reinterpret_cast<uint64_t*>(dst + o)) = *reinterpret_cast<const uint64_t*>(src + o);
+  else if (n == 4) *gbl(reinterpret_cast<uint32_t*>(dst + o)) = *reinterpret_cast<const uint32_t*>(src + o);
+  else if (n == 2) *gbl(reinterpret_cast<uint16_t*>(dst + o)) = *reinterpret_cast<const uint16_t*>(src + o);
+  else gbl(dst)[o] = src[o];
+}
+
 // a11 (second half): copies a payload assembled in LDS at byte phase ph
 // (buf + ph holds its S bytes, ph = the destination's offset inside its
 // 16-byte block) to dal + ph, dal being 16-byte aligned: whole blocks with
-// one 16-byte LDS read and one 16-byte store each, the partial first and
-// last blocks byte by byte.
+// one 16-byte LDS read and one 16-byte store each.  The partial first block
+// [ph, 16) and last block [0, end & 15) are each written as at most four
+// naturally aligned pieces (1, 2, 4 and 8 bytes); a payload inside a single
+// block, byte by byte.
 __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dal, uint32_t ph, uint32_t S, int lane) {
   const uint32_t end = ph + S;
   const uint32_t nblk = (end + 15) >> 4;
@@ -580,9 +591,25 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dal, u
     const uint32_t b_lo = 16 * k, b_hi = b_lo + 16;
     if (b_lo >= ph && b_hi <= end) {
       gstore16(dal + b_lo, *reinterpret_cast<const uint4*>(buf + b_lo));
+    } else if (b_lo < ph && b_hi <= end) {
+      // head: bytes ph .. 15 of the block, pieces in increasing size
+      uint32_t o = ph;
+      for (uint32_t n = 1; n < 16; n <<= 1)
+        if (o & n) {
+          copy_piece(buf, dal, o, n);
+          o += n;
+        }
+    } else if (b_lo >= ph) {
+      // tail: bytes 0 .. (end & 15) - 1 of the block, pieces in decreasing size
+      const uint32_t e = end - b_lo;
+      uint32_t o = b_lo;
+      for (uint32_t n = 8; n >= 1; n >>= 1)
+        if (e & n) {
+          copy_piece(buf, dal, o, n);
+          o += n;
+        }
     } else {
-      const uint32_t from = b_lo > ph ? b_lo : ph, to = b_hi < end ? b_hi : end;
-      for (uint32_t b = from; b < to; ++b) gbl(dal)[b] = buf[b];
+      for (uint32_t b = ph; b < end; ++b) gbl(dal)[b] = buf[b];
     }
   }
 }
