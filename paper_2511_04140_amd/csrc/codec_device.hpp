@@ -79,9 +79,35 @@ template <class T>
 __device__ __forceinline__ global_ptr<T> gbl(T* p) {
   return (global_ptr<T>)p;
 }
+// Constant-address-space views for wave-uniform reads of data no kernel of
+// the launch writes (chunk sizes, offsets, per-chunk metadata, series
+// descriptors, all produced by earlier launches or the caller): with a
+// uniform address they compile to scalar loads, which count against the LDS
+// counter instead of the vector-memory counter, so reading them does not
+// wait for the wave's outstanding HBM stores.  Read only, never written.
+template <class T>
+using const_ptr = __attribute__((address_space(4))) const T*;
+template <class T>
+__device__ __forceinline__ const_ptr<T> cst(const T* p) {
+  return (const_ptr<T>)p;
+}
+
+// Raw buffer stores: out-of-range lanes are dropped by the hardware, so a
+// store with some lanes off needs neither an execution mask nor a branch,
+// and every loop iteration issues the same number of memory instructions.
+// That lets the compiler wait for a prefetched load with an exact count
+// (vmcnt) instead of also waiting for the stores issued after it.
+// Descriptor: base, stride 0, num_records bytes, gfx9-family word 3.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_window(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+constexpr uint32_t kDropOffset = 0x80000000u;  // beyond any window: the store is dropped
+constexpr int kNonTemporal = 2;                 // aux bit: no temporal reuse expected
+
 // 16-byte global load and store (a builtin vector type, which can be read and
 // written through an address-space-qualified pointer).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint4 gload16(const void* p) {
   const u32x4 v = *gbl(reinterpret_cast<const u32x4*>(p));
   return make_uint4(v.x, v.y, v.z, v.w);

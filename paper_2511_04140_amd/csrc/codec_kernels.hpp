@@ -633,6 +633,7 @@ struct Staged {
   const uint8_t* sal;  // 16-byte-aligned start of the payload span
   uint64_t avail;      // readable bytes from sal
   uint32_t S, pad, total;
+  uint32_t full;       // blocks of the span that lie wholly inside the readable bytes
   bool bad;
 };
 
@@ -652,10 +653,15 @@ __device__ __forceinline__ uint4 load_block(const uint8_t* sal, uint64_t avail, 
 // subtracts the offset of its first chunk.  Every size must lie in
 // [3 + ZB, BOUND] of the series' dtype and the series' sizes must add up to
 // its payload byte count (checked by its last chunk); a chunk that fails
-// loads nothing.  Blocks are read whole, except a last block that would
-// pass the end of the payload, which is read byte by byte.
+// loads nothing.  The kStageBlocks loads are always issued, through a raw
+// buffer window over the span's whole blocks (blocks past it come back as
+// zeros without a memory access), so that every iteration of the chunk
+// loop issues the same memory instructions and the wait for them is exact.
+// A last block that would pass the end of the payload is read byte by byte
+// when the payload is stored (stage_store).  With fetch unset (no next
+// chunk) the window is empty.
 __device__ __forceinline__ Staged stage_issue(const DecompressSeries& sd, uint64_t t, const uint64_t* offsets,
-                                              bool relative, int lane_in) {
+                                              bool relative, int lane_in, bool fetch) {
   int lane = lane_in;
   asm volatile("" : "+v"(lane));
   Staged st;
@@ -665,15 +671,16 @@ __device__ __forceinline__ Staged stage_issue(const DecompressSeries& sd, uint64
   const uint32_t lo = f64 ? (uint32_t)TF64::ZB + 3 : (uint32_t)TF32::ZB + 3;
   const uint32_t hi = f64 ? (uint32_t)TF64::BOUND : (uint32_t)TF32::BOUND;
   const uint8_t* payload = sd.in + kHdrBytes + 4 * nc;
-  st.S = uniform(gbl(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes))[c]);
-  const uint64_t base = relative ? uniform64(gbl(offsets)[sd.chunk0]) : 0;
-  const uint64_t off = uniform64(gbl(offsets)[t]) - base;
+  st.S = uniform(cst(reinterpret_cast<const uint32_t*>(sd.in + kHdrBytes))[c]);
+  const uint64_t base = relative ? uniform64(cst(offsets)[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(cst(offsets)[t]) - base;
   st.bad = st.S > hi || st.S < lo || off + st.S > sd.payload_bytes ||
            (c == nc - 1 && off + st.S != sd.payload_bytes);
   st.pad = 0;
   st.total = 0;
   st.sal = payload;
   st.avail = 0;
+  st.full = 0;
   if (!st.bad) {
     const uint8_t* src = payload + off;
     st.pad = uniform((uint32_t)((uintptr_t)src & 15u));
@@ -681,25 +688,35 @@ __device__ __forceinline__ Staged stage_issue(const DecompressSeries& sd, uint64
     st.sal = src - st.pad;
     st.avail = (uint64_t)(payload + sd.payload_bytes - st.sal);
     const uint32_t nblk = (st.total + 15) >> 4;
+    st.full = st.avail >= 16ull * nblk ? nblk : (uint32_t)(st.avail >> 4);
+  }
+  const __amdgpu_buffer_rsrc_t win =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(st.sal), 0, fetch ? (int)(16 * st.full) : 0, 0x00020000);
 #pragma unroll
-    for (int k = 0; k < kStageBlocks; ++k) {
-      const uint32_t i = (uint32_t)lane + 64u * k;
-      if (i < nblk) st.blk[k] = load_block(st.sal, st.avail, i);
-    }
+  for (int k = 0; k < kStageBlocks; ++k) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(win, (int)(16u * ((uint32_t)lane + 64u * k)), 0, 0);
+    st.blk[k] = make_uint4(v.x, v.y, v.z, v.w);
   }
   return st;
 }
 
-// Moves a staged payload into the wave's LDS buffer.
+// Moves a staged payload into the wave's LDS buffer: the prefetched blocks
+// first (their only wait is for the prefetch), then the blocks beyond
+// kStageBlocks per lane, then a last block that passes the end of the
+// readable bytes (the end of a series' stream only).
 __device__ __forceinline__ void stage_store(uint8_t* buf, const Staged& st, int lane) {
   const uint32_t nblk = (st.total + 15) >> 4;
 #pragma unroll
   for (int k = 0; k < kStageBlocks; ++k) {
     const uint32_t i = (uint32_t)lane + 64u * k;
-    if (i < nblk) *reinterpret_cast<uint4*>(buf + 16 * i) = st.blk[k];
+    if (i < st.full) *reinterpret_cast<uint4*>(buf + 16 * i) = st.blk[k];
   }
-  for (uint32_t i = (uint32_t)lane + 64u * kStageBlocks; i < nblk; i += 64)
-    *reinterpret_cast<uint4*>(buf + 16 * i) = load_block(st.sal, st.avail, i);
+  for (uint32_t i = (uint32_t)lane + 64u * kStageBlocks; i < st.full; i += 64)
+    *reinterpret_cast<uint4*>(buf + 16 * i) = gload16(st.sal + 16 * i);
+  if (st.full < nblk) {
+    const uint32_t i = st.full + (uint32_t)lane;  // nblk - full <= 1
+    if (i < nblk) *reinterpret_cast<uint4*>(buf + 16 * i) = load_block(st.sal, st.avail, i);
+  }
 }
 
 // d2-d5 of one chunk whose payload is in LDS (stage_store done).
@@ -718,10 +735,9 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   pad = uniform(pad);
   total = uniform(total);
   bad = uniform((uint32_t)bad) != 0;
-  if (bad) {
-    if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
+  // A chunk that fails a check is decoded all the same (every read below is
+  // bounded, so it only produces garbage) and its stores go through an empty
+  // window: every chunk issues the same memory instructions (see stage_issue).
   wave_lds_sync();
   // chunk header: alpha_max, beta_hat_max, z_1, w, scheme flags
   const uint32_t hb = (lane < 24 && pad + lane < total) ? buf[pad + lane] : 0u;
@@ -783,11 +799,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       plane_put<p>(lo, hi, fld);
     }
   });
-  if (ubad || cur != total) {
-    if (lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wave_lds_sync();
-    return;
-  }
+  const bool err = ubad || cur != total;  // wave-uniform
   // d3: inverse transpose
   xpose16(lo);
   if constexpr (sizeof(U) == 8)
@@ -833,14 +845,26 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   const uint64_t base = c * kChunk;
   const uint64_t rem = sd.n - base;
   const int nv = rem < (uint64_t)kChunk ? (int)rem : (int)kChunk;
-  const global_ptr<U> out = gbl(reinterpret_cast<U*>(sd.out) + base);
+  U* const out = reinterpret_cast<U*>(sd.out) + base;
   constexpr uint32_t kLine = 128 / sizeof(U);
   const int mis = (int)(((uintptr_t)out / sizeof(U)) % kLine);
+  // window from the start of out's line to the chunk's last value: element j
+  // sits at byte (j + mis) * sizeof(U); lanes before the chunk (j < 0, only
+  // in store 0) get kDropOffset, lanes past its end fall outside the window
+  const __amdgpu_buffer_rsrc_t win = store_window(out - mis, err ? 0u : (uint32_t)(mis + nv) * sizeof(U));
 #pragma unroll
   for (int k = 0; k < 17; ++k) {
     const int j = 64 * k + lane - mis;
-    if (j >= 0 && j < nv) __builtin_nontemporal_store(vals[j + (j >> 4)], out + j);
+    const int jr = j < 0 ? 0 : (j < nv ? j : nv - 1);  // an LDS slot of this chunk
+    uint32_t voff = (uint32_t)(64 * k + lane) * sizeof(U);
+    if (k == 0 && j < 0) voff = kDropOffset;
+    if constexpr (sizeof(U) == 8)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, vals[jr + (jr >> 4)]), win, (int)voff, 0,
+                                            kNonTemporal);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(vals[jr + (jr >> 4)], win, (int)voff, 0, kNonTemporal);
   }
+  if (err && lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   wave_lds_sync();
 }
 
@@ -859,14 +883,14 @@ __device__ __forceinline__ Series find_series(const Series& one, const Series* m
   uint32_t lo = 0, hi = ns - 1;  // last series with chunk0 <= t
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
-    if (gbl(many)[mid].chunk0 <= t) lo = mid;
+    if (cst(many)[mid].chunk0 <= t) lo = mid;
     else hi = mid - 1;
   }
-  // the descriptor as 8-byte global loads (a struct copy through an
+  // the descriptor as 8-byte scalar loads (a struct copy through an
   // address-space-qualified pointer is not available in C++)
   static_assert(sizeof(Series) % 8 == 0, "descriptor made of 8-byte words");
   uint64_t w[sizeof(Series) / 8];
-  const global_ptr<const uint64_t> q = gbl(reinterpret_cast<const uint64_t*>(many + lo));
+  const const_ptr<uint64_t> q = cst(reinterpret_cast<const uint64_t*>(many + lo));
 #pragma unroll
   for (uint32_t i = 0; i < sizeof(Series) / 8; ++i) w[i] = q[i];
   Series s;
@@ -935,7 +959,7 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   const uint64_t c = t - sd.chunk0;
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
   if (!loaded) load_chunk<T>(sd, c, lane, vb);
-  const global_ptr<const uint64_t> mp = gbl(reinterpret_cast<const uint64_t*>(a.meta + t));
+  const const_ptr<uint64_t> mp = cst(reinterpret_cast<const uint64_t*>(a.meta + t));
   const uint64_t flags = uniform64(mp[0]);
   const uint64_t m1 = uniform64(mp[1]);
   const uint32_t S = (uint32_t)m1;
@@ -946,8 +970,8 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   prefetch();
   // the payload goes to dst; it is assembled at dst's 16-byte phase so that
   // the copy moves whole aligned blocks
-  const uint64_t base = a.relative ? uniform64(gbl(a.offsets)[sd.chunk0]) : 0;
-  const uint64_t off = uniform64(gbl(a.offsets)[t]) - base;
+  const uint64_t base = a.relative ? uniform64(cst(a.offsets)[sd.chunk0]) : 0;
+  const uint64_t off = uniform64(cst(a.offsets)[t]) - base;
   uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
   assemble_payload<T>(buf + ph, cp, flags, S, lane);
@@ -1038,7 +1062,16 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
   uint64_t t = (uint64_t)blockIdx.x * kWavesD + wid;
   if (t >= a.total_chunks) return;
   DecompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
-  Staged st = stage_issue(sd, t + a.t0, a.offsets, a.relative != 0, lane);
+  Staged st = stage_issue(sd, t + a.t0, a.offsets, a.relative != 0, lane, true);
+  // Seventeen stores with an empty window (dropped, no memory access): the
+  // loop is then entered, as it is re-entered, with the value stores of a
+  // chunk issued after the prefetch, so the wait for the prefetch in
+  // stage_store can leave those stores in flight.
+  {
+    const __amdgpu_buffer_rsrc_t none = store_window(buf, 0);
+#pragma unroll
+    for (int k = 0; k < 17; ++k) __builtin_amdgcn_raw_buffer_store_b32(0u, none, 4 * (lane + 64 * k), 0, kNonTemporal);
+  }
   for (;;) {
     stage_store(buf, st, lane);
     const DecompressSeries cur = sd;
@@ -1047,10 +1080,11 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
     const bool bad = st.bad;
     const uint64_t tn = t + a.total_waves;
     const bool more = tn < a.total_chunks;
-    if (more) {
-      sd = find_series(a.one, a.many, a.nseries, tn + a.t0);
-      st = stage_issue(sd, tn + a.t0, a.offsets, a.relative != 0, lane);
-    }
+    // the next chunk's loads; past the last chunk the same instructions run
+    // on the current chunk with an empty window (no memory access)
+    const uint64_t tq = more ? tn : t;
+    sd = find_series(a.one, a.many, a.nseries, tq + a.t0);
+    st = stage_issue(sd, tq + a.t0, a.offsets, a.relative != 0, lane, more);
     dispatch(cur, c, S, pad, total, bad);
     if (!more) break;
     t = tn;
