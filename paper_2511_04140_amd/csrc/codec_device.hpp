@@ -246,6 +246,59 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
   return ((uint64_t)wave_or32((uint32_t)(v >> 32)) << 32) | wave_or32((uint32_t)v);
 }
 
+// Wave-wide sum (uniform result): the same row steps as the OR above
+// combine disjoint lane groups, so they add each lane once.
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppHalfMirror>(v);
+  v += dpp<kDppMirror>(v);
+  return rl(v, 0) + rl(v, 16) + rl(v, 32) + rl(v, 48);
+}
+
+// Lane L receives v from lane L ^ B: quad permutes for 1 and 2, a row
+// rotate by 8 for 8, a swizzle inside 32-lane halves for 4 and 16, a
+// backward permute for 32.
+constexpr int kDppRor8 = 0x128;
+template <int B>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lane) {
+  if constexpr (B == 1) return dpp<kDppXor1>(v);
+  else if constexpr (B == 2) return dpp<kDppXor2>(v);
+  else if constexpr (B == 8) return dpp<kDppRor8>(v);
+  else if constexpr (B == 4 || B == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (B << 10));
+  else return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)v);
+}
+
+// 64 x 64 bit-matrix transpose across the wave (rows = lanes): afterwards
+// bit L of lane p's word is bit p of lane L's word before.  Recursive block
+// swaps: lanes L and L ^ B exchange the off-diagonal B x B blocks, B = 32
+// (the two dwords), then 16, 8, 4, 2, 1 inside each dword.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  {
+    const bool up = lane & 32;
+    const uint32_t r = xor_lane<32>(up ? lo : hi, lane);
+    if (up) lo = r;
+    else hi = r;
+  }
+  auto stage = [&](auto b_tag, uint32_t m) {  // m: the bits whose index has bit B set
+    constexpr int B = decltype(b_tag)::value;
+    const bool up = lane & B;
+    auto one = [&](uint32_t& v) {
+      const uint32_t send = up ? (v & ~m) << B : (v & m) >> B;
+      v = (v & (up ? m : ~m)) | xor_lane<B>(send, lane);
+    };
+    one(lo);
+    one(hi);
+  };
+  stage(std::integral_constant<int, 16>{}, 0xFFFF0000u);
+  stage(std::integral_constant<int, 8>{}, 0xFF00FF00u);
+  stage(std::integral_constant<int, 4>{}, 0xF0F0F0F0u);
+  stage(std::integral_constant<int, 2>{}, 0xCCCCCCCCu);
+  stage(std::integral_constant<int, 1>{}, 0xAAAAAAAAu);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Wave-wide unsigned maximum (uniform result).
 __device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
   auto step = [&](auto ctrl_tag) {

@@ -499,27 +499,21 @@ struct ChunkStats {
 
 // a8-a9 from the byte ORs of the size pass: byte 2L of row p (elements
 // 16L..16L+7, plane p) is non-zero iff bit p of or0 is set; byte 2L+1 the
-// same with or1, so the row's non-zero bytes are counted without the
-// transpose.  The kVarSparse / kVarDense ablations fix every row's scheme
-// instead.
+// same with or1.  A bit-matrix transpose across the wave hands lane p the
+// 64 lane bits of plane p, so lane p counts row p's non-zero bytes, decides
+// its scheme and its size, and one ballot and one wave sum finish the chunk.
+// The kVarSparse / kVarDense ablations fix every row's scheme instead.
 template <class T, int V = kVarFalcon>
-__device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp) {
+__device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp, int lane) {
   const uint32_t w = cp.w;
-  uint64_t flags = 0;
-  uint32_t rows = 0;
-  for_planes_down<T::W - 1>([&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    if (p < (int)w) {
-      const uint64_t E = ballot(((cp.or0 >> p) & 1) != 0), O = ballot(((cp.or1 >> p) & 1) != 0);
-      const uint32_t nnz = (uint32_t)(__popcll(E) + __popcll(O));
-      const bool dense = V == kVarDense || (V != kVarSparse && nnz >= 112);
-      flags |= (uint64_t)dense << p;
-      rows += dense ? 128u : 16u + nnz;
-    }
-  });
+  const uint64_t t0 = wave_transpose64(cp.or0, lane), t1 = wave_transpose64(cp.or1, lane);
+  const uint32_t nnz = (uint32_t)(__popcll(t0) + __popcll(t1));  // non-zero bytes of row `lane`
+  const bool row = (uint32_t)lane < w;
+  const bool dense = row && (V == kVarDense || (V != kVarSparse && nnz >= 112));
+  const uint32_t bytes = !row ? 0u : dense ? 128u : 16u + nnz;
   ChunkStats st;
-  st.flags = flags;
-  st.S = 3 + T::ZB + ((w + 7) >> 3) + rows;
+  st.flags = ballot(dense);
+  st.S = 3 + T::ZB + ((w + 7) >> 3) + wave_sum32(bytes);
   return st;
 }
 
@@ -936,7 +930,7 @@ __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, c
   ChunkPlanes cp;
   compress_front<T, false, V>(tab, buf, vb, lane, cp);
   prefetch();
-  const ChunkStats st = chunk_stats_or<T, V>(cp);
+  const ChunkStats st = chunk_stats_or<T, V>(cp, lane);
   if (lane == 0) {
     ChunkMeta m;
     m.flags = st.flags;
