@@ -60,7 +60,8 @@ typedef enum {
 typedef struct falcon_ctx falcon_ctx;
 
 /* Creates a context on HIP device `device`: a stream, pinned staging and
- * device scratch (chunk status words for the prefix sum, counters).
+ * device scratch (per-chunk metadata, sizes and offsets for the prefix sum,
+ * an error word), grown on demand.
  * Returns FALCON_ERR_DEVICE if the device cannot be used. */
 falcon_status falcon_create(int device, falcon_ctx** out);
 
@@ -223,9 +224,10 @@ typedef struct falcon_plan_info {
 } falcon_plan_info;
 
 /* Compresses count series in one launch sequence (no tuning, no graph):
- * every chunk of every series is a work item of the same persistent
- * kernel, whose decoupled look-back (Sec. 3.4) runs per series.  Sets each
- * s[i].out_len.  Series are checked on the host first: a bad descriptor
+ * every chunk of every series is a work item of the same size pass, one
+ * scan turns the sizes of all series into offsets (Sec. 3.4, each series
+ * relative to its first chunk), and the write pass places every chunk.
+ * Sets each s[i].out_len.  Series are checked on the host first: a bad descriptor
  * returns FALCON_ERR_INVALID_ARG / FALCON_ERR_BUFFER_TOO_SMALL before any
  * launch.  Synchronous. */
 falcon_status falcon_compress_batch(falcon_ctx* ctx, falcon_series* s, size_t count, void* stream);
