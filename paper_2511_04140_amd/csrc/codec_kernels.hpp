@@ -772,8 +772,10 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       const bool dense = (flags >> p) & 1;
       uint32_t nnz = 0;  // sparse rows: non-zero bytes after the bitmap
       if (dense) {
-        const uint32_t a0 = min(cur + 2 * (uint32_t)lane, kLim - 1);
-        fld = (uint32_t)buf[a0] | ((uint32_t)buf[a0 + 1] << 8);
+        // two byte reads: a 16-bit LDS access at an odd address is far
+        // slower than two byte accesses
+        const uint32_t a0 = min(cur + 2 * (uint32_t)lane, kLim - 1), a1 = min(cur + 2 * (uint32_t)lane + 1, kLim);
+        fld = (uint32_t)buf[a0] | ((uint32_t)buf[a1] << 8);
       } else {
         // bitmap byte L/4 covers this lane's row bytes 2L and 2L+1 (MSB first)
         const uint32_t bm = buf[min(cur + ((uint32_t)lane >> 2), kLim)];
