@@ -147,6 +147,9 @@ struct TF64 {
   static __device__ __forceinline__ F mu_scale() { return 0x1p-52; }
   static __device__ __forceinline__ F rnd(F x) { return __builtin_rint(x); }
   static __device__ __forceinline__ F abs(F x) { return __builtin_fabs(x); }
+  static __device__ __forceinline__ F fma(F a, F b, F c) { return __builtin_fma(a, b, c); }
+  static __device__ __forceinline__ F ldexp(F x, int k) { return __builtin_ldexp(x, k); }
+  static constexpr U MANT_MASK = (1ull << MANT) - 1;
   static __device__ __forceinline__ int expf(U b) { return (int)((b >> MANT) & EXPMAX); }
   static __device__ __forceinline__ U mag(U b) { return b & 0x7FFFFFFFFFFFFFFFull; }
   // r is an integer with |r| < 2^51: r + 1.5 * 2^52 is exact and its low
@@ -174,6 +177,9 @@ struct TF32 {
   static __device__ __forceinline__ F mu_scale() { return 0x1p-23f; }
   static __device__ __forceinline__ F rnd(F x) { return __builtin_rintf(x); }
   static __device__ __forceinline__ F abs(F x) { return __builtin_fabsf(x); }
+  static __device__ __forceinline__ F fma(F a, F b, F c) { return __builtin_fmaf(a, b, c); }
+  static __device__ __forceinline__ F ldexp(F x, int k) { return __builtin_ldexpf(x, k); }
+  static constexpr U MANT_MASK = (1u << MANT) - 1;
   static __device__ __forceinline__ int expf(U b) { return (int)((b >> MANT) & EXPMAX); }
   static __device__ __forceinline__ U mag(U b) { return b & 0x7FFFFFFFu; }
   static __device__ __forceinline__ S to_int(F r) {

@@ -49,13 +49,36 @@ __device__ __forceinline__ bool exact_test(typename T::U b, typename T::F P, typ
   return x == r;
 }
 
+// The recover check of Alg. 2, r / P == v after IEEE division, without the
+// division: the quotient rounds to v exactly when the residual r - v * P
+// (one fused multiply-add, rounded once, which keeps it on the right side of
+// any representable bound) lies inside v's rounding interval scaled by P:
+// half an ulp of v away from zero, and toward zero a quarter ulp when |v|
+// is a power of two (the binade below is twice as fine).  A residual exactly
+// on the bound is a tie and takes the division.  v is a normal number here
+// (T1) and P >= 1, so the bound P * ulp(v) / 2 is an exact power-of-two
+// scaling of P.
+template <class T>
+__device__ __forceinline__ bool recovers(typename T::U b, typename T::F r, typename T::F P) {
+  using F = typename T::F;
+  const F v = T::f(b);
+  const F e = T::fma(-v, P, r);
+  const F half = T::ldexp(P, T::expf(b) - T::BIAS - T::MANT - 1);
+  const bool toward_zero = (e > 0) != (v > 0);
+  const F tol = (toward_zero && (b & T::MANT_MASK) == 0) ? half * (F)0.5 : half;
+  const F ae = T::abs(e);
+  if (ae < tol) return true;
+  if (ae > tol) return false;
+  return T::u(r / P) == b;
+}
+
 // Stopping test plus the recover check of Alg. 2: round(v (x) 10^a) / 10^a
 // must give back v bit for bit.
 template <class T>
 __device__ __forceinline__ bool full_test(typename T::U b, typename T::F P) {
   typename T::F r;
   const bool ok = eps_test<T>(b, P, r);
-  return ok && T::u(r / P) == b;
+  return ok && recovers<T>(b, r, P);
 }
 
 // bit k of m |= c.  The shift amount is made opaque so that the compiler
@@ -92,7 +115,7 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
           typename T::F r;
           if (ELF ? exact_test<T>(v, P, r) : eps_test<T>(v, P, r)) {
             done = true;
-            if (T::u(r / P) != v) exc = true;
+            if (!recovers<T>(v, r, P)) exc = true;
             else amax = max(amax, a);
           }
         }

@@ -212,3 +212,89 @@ def test_own_limit_shortcut(dt):
         thr = spec.bits(spec.P[maxfl])[()]
         shortcut = np.full(m.shape, lstar == spec.A) | (m >= thr)
         assert np.array_equal(lim == lstar, shortcut)
+
+
+def _recovers_rule_f64(v, r, P):
+    """The GPU's division-free recover check (recovers() in
+    codec_kernels.hpp), restated with exact rationals; None for a tie."""
+    from fractions import Fraction
+    e = float(Fraction(r) - Fraction(v) * Fraction(P))      # one rounding, as the FMA
+    b = int(np.float64(v).view(np.uint64))
+    half = float(P) * 2.0 ** (((b >> 52) & 0x7FF) - 1076)   # P * ulp(v) / 2
+    toward_zero = (e > 0) != (v > 0)
+    tol = half / 2 if toward_zero and (b & ((1 << 52) - 1)) == 0 else half
+    if abs(e) < tol:
+        return True
+    if abs(e) > tol:
+        return False
+    return None
+
+
+def _recovers_rule_f32(v, r, P):
+    e = np.float32(float(r) - float(v) * float(P))           # exact in binary64, then one rounding
+    b = int(np.float32(v).view(np.uint32))
+    half = np.float32(float(P) * 2.0 ** (((b >> 23) & 0xFF) - 151))
+    toward_zero = (e > 0) != (v > 0)
+    tol = np.float32(half / 2) if toward_zero and (b & ((1 << 23) - 1)) == 0 else half
+    if abs(e) < tol:
+        return True
+    if abs(e) > tol:
+        return False
+    return None
+
+
+def test_division_free_recover_check():
+    """The recover check of Alg. 2 (r / 10^a must give back v after IEEE
+    division) is taken on the GPU from the sign and size of the fused
+    residual r - v * 10^a against v's rounding interval.  It must agree with
+    the division on decimal strings, random magnitudes, powers of two (whose
+    interval is lopsided) and their neighbours, in both precisions."""
+    rng = np.random.default_rng(2511)
+    checked = 0
+    for i in range(6000):
+        kind = i % 4
+        if kind == 0:
+            v = float(f"{int(rng.integers(1, 10 ** int(rng.integers(1, 16))))}e-{int(rng.integers(0, 16))}")
+        elif kind == 1:
+            v = float(rng.standard_normal() * 10.0 ** rng.integers(-20, 15))
+        elif kind == 2:
+            v = float(2.0 ** int(rng.integers(-60, 50)))
+        else:
+            v = float(np.nextafter(2.0 ** int(rng.integers(-30, 40)), 0.0))
+        v = -v if rng.random() < 0.5 else v
+        if v == 0 or abs(v) < 1e-22 or abs(v) >= 1e15:
+            continue
+        for a in range(0, 23):
+            P = 10.0 ** a
+            x = v * P
+            if abs(x) >= 2.0 ** 52:
+                break
+            r = float(np.rint(x))
+            if r == 0:
+                continue
+            got = _recovers_rule_f64(v, r, P)
+            if got is not None:
+                assert got == (r / P == v), (v, a)
+                checked += 1
+    assert checked > 50000
+    for i in range(3000):
+        kind = i % 3
+        if kind == 0:
+            v = np.float32(float(f"{int(rng.integers(1, 10 ** int(rng.integers(1, 8))))}e-{int(rng.integers(0, 8))}"))
+        elif kind == 1:
+            v = np.float32(rng.standard_normal() * 10.0 ** rng.integers(-9, 6))
+        else:
+            v = np.nextafter(np.float32(2.0 ** int(rng.integers(-20, 19))), np.float32(0))
+        if v == 0 or abs(v) < 1e-10 or abs(v) >= 1e6:
+            continue
+        for a in range(0, 11):
+            P = np.float32(10.0 ** a)
+            x = np.float32(v * P)
+            if abs(float(x)) >= 2.0 ** 23:
+                break
+            r = np.rint(x)
+            if r == 0:
+                continue
+            got = _recovers_rule_f32(v, r, P)
+            if got is not None:
+                assert got == bool(np.float32(r / P) == v), (v, a)
