@@ -787,6 +787,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   uint32_t cur = uniform(pad + 3 + T::ZB + nflag);
   bool ubad = uniform((uint32_t)bad) != 0;
   constexpr uint32_t kLim = kWaveLds - 1;
+  static_assert(15 + T::BOUND + 144 <= kLim, "clamped row reads of a valid chunk are never moved");
   const uint32_t sh = 6u - 2u * ((uint32_t)lane & 3u);  // bitmap bit of row byte 2L + 1
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
@@ -794,20 +795,24 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       uint32_t fld;
       const bool dense = (flags >> p) & 1;
       uint32_t nnz = 0;  // sparse rows: non-zero bytes after the bitmap
+      // reads are kept inside the buffer by clamping the (scalar) cursor: in
+      // a valid chunk every row ends by total <= 15 + BOUND, below both
+      // clamps, so they never move a read; a corrupt chunk is reported
+      // through ubad
       if (dense) {
         // two byte reads: a 16-bit LDS access at an odd address is far
         // slower than two byte accesses
-        const uint32_t a0 = min(cur + 2 * (uint32_t)lane, kLim - 1), a1 = min(cur + 2 * (uint32_t)lane + 1, kLim);
-        fld = (uint32_t)buf[a0] | ((uint32_t)buf[a1] << 8);
+        const uint8_t* q = buf + min(cur, kLim - 128) + 2 * (uint32_t)lane;
+        fld = (uint32_t)q[0] | ((uint32_t)q[1] << 8);
       } else {
+        const uint8_t* q = buf + min(cur, kLim - 145);
         // bitmap byte L/4 covers this lane's row bytes 2L and 2L+1 (MSB first)
-        const uint32_t bm = buf[min(cur + ((uint32_t)lane >> 2), kLim)];
+        const uint32_t bm = q[(uint32_t)lane >> 2];
         const uint32_t nz0 = (bm >> (sh + 1)) & 1u, nz1 = (bm >> sh) & 1u;
         const uint64_t E = ballot(nz0 != 0), O = ballot(nz1 != 0);
         nnz = (uint32_t)(__popcll(E) + __popcll(O));
-        const uint32_t rank = mbcnt(E) + mbcnt(O);
-        const uint32_t d0 = cur + 16 + rank;
-        const uint32_t r0 = buf[min(d0, kLim)], r1 = buf[min(d0 + nz0, kLim)];
+        const uint8_t* d = q + 16 + mbcnt(E) + mbcnt(O);  // rank < 128
+        const uint32_t r0 = d[0], r1 = d[nz0];
         fld = (nz0 ? r0 : 0u) | ((nz1 ? r1 : 0u) << 8);
       }
       // the row's extent, checked and stepped over after the join so that
