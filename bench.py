@@ -348,6 +348,85 @@ def ablation(codec, torch, x_c2, reps=5):
     return res
 
 
+def full_range(codec, torch, wave_bytes=12 << 30, reps=3):
+    """The 10,000-series batch with the full length range, log-uniform on
+    [2^10, 2^24] values (about 109 GB, float64 and float32 mixed), streamed
+    through the GPU in waves: the series are generated on the host a wave
+    (at most wave_bytes of input) at a time, copied to the device, and each
+    wave is compressed and decompressed by tuned, graph-captured batch plans
+    (best of reps runs each).  Reports the device throughput over all waves
+    and checks that every series round-trips."""
+    import numpy as np
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    log = lambda m: print(f"[full-range] {m}", file=sys.stderr, flush=True)
+    lens, is64, places = W.batch_layout(hi=1 << 24)
+    nbytes = lens * np.where(is64, 8, 4)
+    waves, cur, acc = [], [], 0
+    for i in range(len(lens)):
+        if cur and acc + nbytes[i] > wave_bytes:
+            waves.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += int(nbytes[i])
+    waves.append(cur)
+    tot = {"bytes": 0, "stream_bytes": 0, "compress_s": 0.0, "decompress_s": 0.0, "generate_s": 0.0, "h2d_s": 0.0}
+    identical = True
+    for k, wv in enumerate(waves):
+        t0 = time.perf_counter()
+        xs = W.batch_series(hi=1 << 24, select=wv)
+        t1 = time.perf_counter()
+        xd = [torch.from_numpy(x).cuda() for x in xs]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del xs
+        tot["generate_s"] += t1 - t0
+        tot["h2d_s"] += t2 - t1
+        plan = codec.plan_compress(xd, tune=True, graph=True)
+        plan.run(fetch=False)
+        tc = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            plan.run(fetch=False)
+            torch.cuda.synchronize()
+            tc.append(time.perf_counter() - a)
+        streams = plan.run()
+        counts = [x.numel() for x in xd]
+        dts = [x.dtype for x in xd]
+        dplan = codec.plan_decompress(streams, counts, dts, tune=True, graph=True)
+        dplan.run(fetch=False)
+        td = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            dplan.run(fetch=False)
+            torch.cuda.synchronize()
+            td.append(time.perf_counter() - a)
+        ys = dplan.run()
+        ok = all(torch.equal(y.view(torch.uint8), x.view(torch.uint8)) for x, y in zip(xd, ys))
+        identical = identical and ok
+        wb = sum(x.numel() * x.element_size() for x in xd)
+        tot["bytes"] += wb
+        tot["stream_bytes"] += sum(s_.numel() for s_ in streams)
+        tot["compress_s"] += min(tc)
+        tot["decompress_s"] += min(td)
+        log(f"wave {k + 1}/{len(waves)}: {len(wv)} series, {wb / 1e9:.2f} GB, compress {wb / min(tc) / 1e9:.0f} GB/s, "
+            f"decompress {wb / min(td) / 1e9:.0f} GB/s, identical {ok}")
+        dplan.close()
+        plan.close()
+        del xd, streams, ys, plan, dplan
+        torch.cuda.empty_cache()
+    return {"series": int(len(lens)), "waves": len(waves), "bytes": int(tot["bytes"]),
+            "values_min_max": [int(lens.min()), int(lens.max())],
+            "ratio": round(tot["stream_bytes"] / tot["bytes"], 6),
+            "compress_gbps": round(tot["bytes"] / tot["compress_s"] / 1e9, 2),
+            "decompress_gbps": round(tot["bytes"] / tot["decompress_s"] / 1e9, 2),
+            "host_generate_s": round(tot["generate_s"], 1), "h2d_pageable_s": round(tot["h2d_s"], 1),
+            "timing": "device-resident plan runs per wave (best of %d), summed over waves" % reps,
+            "identical": identical}
+
+
 def _device_rates(codec, torch, xd, reps=5):
     """Median kernel time of compression and of decompression over reps
     calls on a device-resident tensor; returns (ratio, compress GB/s,
@@ -444,6 +523,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 10,000-series batched launch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the ablation-variant measurement")
+    ap.add_argument("--full-range", action="store_true",
+                    help="also stream the full-length-range 10,000-series batch (about 109 GB) through the GPU")
     ap.add_argument("--studies", action="store_true",
                     help="also run the parameter studies (beta, data size, pipeline batch size)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -577,6 +658,8 @@ def main():
     if not args.no_ablation:
         out["ablation"] = ablation(codec, torch, x)
         log(f"ablation: {out['ablation']}")
+    if args.full_range:
+        out["full_range"] = full_range(codec, torch)
     if args.studies:
         out["studies"] = studies(codec, torch)
         torch.cuda.empty_cache()

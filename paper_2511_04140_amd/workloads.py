@@ -203,27 +203,38 @@ def _sensor_values(rng, n: int, d: int, phase: int) -> np.ndarray:
     return np.rint(x * s) / s + 0.0
 
 
-def batch_series(count: int = 10000, seed: int = 4, lo: int = 1024, hi: int = 369_000,
-                 f64_share: float = 0.6, max_places: int = 6) -> list:
-    """Independent series for batched launches: lengths log-uniform on
-    [lo, hi] values, a shuffled f64_share of them float64 and the rest
-    float32, d ~ U{0..max_places} decimal places per series, sensor-like
-    values without outliers or specials.  With the defaults the expected
-    total is about 4 GB (10,000 x 62,500 values x 6.4 bytes)."""
+def batch_layout(count: int = 10000, seed: int = 4, lo: int = 1024, hi: int = 369_000,
+                 f64_share: float = 0.6, max_places: int = 6):
+    """The shape of a batch of independent series: (lengths, is_float64,
+    decimal places), lengths log-uniform on [lo, hi] values, a shuffled
+    f64_share of the series float64, d ~ U{0..max_places}."""
     rng = np.random.default_rng([seed, 0])
     n64 = int(round(count * f64_share))
     is64 = np.zeros(count, bool)
     is64[rng.permutation(count)[:n64]] = True
     lens = np.exp(rng.uniform(np.log(lo), np.log(hi), count)).astype(np.int64)
     places = rng.integers(0, max_places + 1, count)
+    return lens, is64, places
 
-    def one(i):
-        r = np.random.default_rng([seed, 1, i])
-        v = _sensor_values(r, int(lens[i]), int(places[i]), int(r.integers(0, 10000)))
-        return v if is64[i] else v.astype(np.float32)
 
+def batch_series_one(i: int, lens, is64, places, seed: int = 4) -> np.ndarray:
+    """Series i of a batch layout: sensor-like values without outliers or
+    specials at its decimal places, float32 where the layout says so."""
+    r = np.random.default_rng([seed, 1, i])
+    v = _sensor_values(r, int(lens[i]), int(places[i]), int(r.integers(0, 10000)))
+    return v if is64[i] else v.astype(np.float32)
+
+
+def batch_series(count: int = 10000, seed: int = 4, lo: int = 1024, hi: int = 369_000,
+                 f64_share: float = 0.6, max_places: int = 6, select=None) -> list:
+    """Independent series for batched launches (batch_layout, then
+    batch_series_one for each).  With the defaults the expected total is
+    about 4 GB (10,000 x 62,500 values x 6.4 bytes); with hi = 2^24 it is
+    about 110 GB, which callers generate a subset (select) at a time."""
+    lens, is64, places = batch_layout(count, seed, lo, hi, f64_share, max_places)
+    idx = range(count) if select is None else select
     with _pool() as ex:
-        return list(ex.map(one, range(count)))
+        return list(ex.map(lambda i: batch_series_one(i, lens, is64, places, seed), idx))
 
 
 def serving_payloads(count: int = 256, seed: int = 5, lo_bytes: int = 4096, hi_bytes: int = 64 << 20) -> list:
