@@ -789,6 +789,12 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   constexpr uint32_t kLim = kWaveLds - 1;
   static_assert(15 + T::BOUND + 144 <= kLim, "clamped row reads of a valid chunk are never moved");
   const uint32_t sh = 6u - 2u * ((uint32_t)lane & 3u);  // bitmap bit of row byte 2L + 1
+  // a dense row's bytes for this lane sit at 2L and 2L + 1 past the cursor;
+  // the second offset is opaque so that the compiler cannot merge the two
+  // byte reads into one 16-bit read, which is slow at odd addresses
+  const uint32_t l2 = 2u * (uint32_t)lane;
+  uint32_t l2p = l2 + 1u;
+  asm volatile("" : "+v"(l2p));
   for_planes_down<T::W - 1>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
     if (p < (int)w) {
@@ -800,10 +806,9 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       // clamps, so they never move a read; a corrupt chunk is reported
       // through ubad
       if (dense) {
-        // two byte reads: a 16-bit LDS access at an odd address is far
-        // slower than two byte accesses
-        const uint8_t* q = buf + min(cur, kLim - 128) + 2 * (uint32_t)lane;
-        fld = (uint32_t)q[0] | ((uint32_t)q[1] << 8);
+        // two byte reads (see l2p above)
+        const uint32_t c0 = min(cur, kLim - 128);
+        fld = (uint32_t)buf[c0 + l2] | ((uint32_t)buf[c0 + l2p] << 8);
       } else {
         const uint8_t* q = buf + min(cur, kLim - 145);
         // bitmap byte L/4 covers this lane's row bytes 2L and 2L+1 (MSB first)
