@@ -881,17 +881,23 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   // sits at byte (j + mis) * sizeof(U); lanes before the chunk (j < 0, only
   // in store 0) get kDropOffset, lanes past its end fall outside the window
   const __amdgpu_buffer_rsrc_t win = store_window(out - mis, err ? 0u : (uint32_t)(mis + nv) * sizeof(U));
+  // Store k takes element j = 64k + a0 from slot j + (j >> 4) = 68k + s0.
+  // Only stores 0 and 16 can reach past the chunk's slots (j < 0 or
+  // j > 1024), so only they clamp; a lane whose j is not below nv reads a
+  // slot inside the buffer, and its store falls outside the window.
+  const int a0 = lane - mis;
+  const int s0 = a0 + (a0 >> 4);
+  const int j0 = a0 < 0 ? 0 : a0;
+  const int j16 = min(64 * 16 + a0, kChunk - 1);
+  const uint32_t vl = (uint32_t)lane * sizeof(U);
 #pragma unroll
   for (int k = 0; k < 17; ++k) {
-    const int j = 64 * k + lane - mis;
-    const int jr = j < 0 ? 0 : (j < nv ? j : nv - 1);  // an LDS slot of this chunk
-    uint32_t voff = (uint32_t)(64 * k + lane) * sizeof(U);
-    if (k == 0 && j < 0) voff = kDropOffset;
+    const U v = k == 0 ? vals[j0 + (j0 >> 4)] : k == 16 ? vals[j16 + (j16 >> 4)] : vals[68 * k + s0];
+    const uint32_t voff = (k == 0 && a0 < 0) ? kDropOffset : vl + 64u * k * sizeof(U);
     if constexpr (sizeof(U) == 8)
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, vals[jr + (jr >> 4)]), win, (int)voff, 0,
-                                            kNonTemporal);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), win, (int)voff, 0, kNonTemporal);
     else
-      __builtin_amdgcn_raw_buffer_store_b32(vals[jr + (jr >> 4)], win, (int)voff, 0, kNonTemporal);
+      __builtin_amdgcn_raw_buffer_store_b32(v, win, (int)voff, 0, kNonTemporal);
   }
   if (err && lane == 0) __hip_atomic_store(&ctl->error, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   wave_lds_sync();
