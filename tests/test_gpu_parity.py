@@ -119,6 +119,28 @@ def test_ragged_lengths(codec, orc, n):
     _roundtrip_and_parity(codec, orc, W.decimal_f32(n, seed=n, places=3), f"dec32_{n}")
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_decompress_into_unaligned_views(codec, orc, dt):
+    """Decoding into a view at every element phase of a 128-byte line: the
+    value stores of every chunk start at each possible misalignment, the
+    last chunk is partial, and no byte outside the view is written."""
+    from paper_2511_04140_amd import workloads as W
+    n = 3 * 1025 + 77
+    x = W.walk_f64(n, seed=41) if dt == "f64" else W.decimal_f32(n, seed=41, places=3)
+    s = torch.from_numpy(np.frombuffer(orc.compress(x), np.uint8).copy()).cuda()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    line = 128 // x.itemsize
+    guard = torch.full((n + 2 * line + 64,), -7.25, dtype=tdt, device="cuda")
+    for k in range(line):
+        _log(f"[parity] unaligned view {dt} phase {k}")
+        buf = guard.clone()
+        y = codec.decompress(s, out=buf[line + k: line + k + n + 5])
+        assert y.numel() == n
+        got = buf.cpu().numpy()
+        assert np.array_equal(got[line + k: line + k + n].view(np.uint8), x.view(np.uint8)), k
+        assert (got[: line + k] == -7.25).all() and (got[line + k + n:] == -7.25).all(), k
+
+
 def test_empty(codec, orc):
     for dt in (np.float64, np.float32):
         x = np.zeros(0, dt)
