@@ -91,6 +91,41 @@ def cpu_baseline(x, budget_s=12.0):
     }
 
 
+def oracle_small_case(threads=None):
+    """The 2^20-value walk (Gaussian steps from 100.0, two decimals) through
+    the oracle: compression and decompression seconds on one thread, then on
+    `threads` threads over chunk-aligned slices of the same values (each
+    slice a stream of its own; the oracle's C calls release the GIL).  Every
+    round trip is checked."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle
+    import numpy as np
+    from paper_2511_04140_amd import workloads as W
+    x = W.walk_f64(1 << 20, seed=1)
+    t0 = time.perf_counter()
+    s = oracle.compress(x)
+    t1 = time.perf_counter()
+    y = oracle.decompress(s)
+    t2 = time.perf_counter()
+    assert np.array_equal(y.view(np.uint8), x.view(np.uint8))
+    nt = threads or min(16, os.cpu_count() or 1)
+    nc = (x.size + 1024) // 1025
+    cuts = [min(x.size, 1025 * (nc * k // nt)) for k in range(nt + 1)]
+    parts = [x[cuts[k]:cuts[k + 1]] for k in range(nt)]
+    with ThreadPoolExecutor(nt) as ex:
+        t3 = time.perf_counter()
+        ss = list(ex.map(oracle.compress, parts))
+        t4 = time.perf_counter()
+        ys = list(ex.map(oracle.decompress, ss))
+        t5 = time.perf_counter()
+    assert all(np.array_equal(a.view(np.uint8), b.view(np.uint8)) for a, b in zip(parts, ys))
+    return {"workload": "walk_f64: 1,048,576 float64 values (8 MiB), Gaussian walk from 100.0, 2 decimals",
+            "ratio": round(len(s) / x.nbytes, 6),
+            "one_thread": {"compress_s": round(t1 - t0, 4), "decompress_s": round(t2 - t1, 4)},
+            "threads": nt,
+            "all_threads": {"compress_s": round(t4 - t3, 4), "decompress_s": round(t5 - t4, 4)}}
+
+
 def host_pipeline(codec, x, torch, reps=2):
     """Host -> host through the stream pipeline (Alg. 1): the default
     geometry (4 streams, 1024-chunk batches) from pinned and from pageable
@@ -665,6 +700,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x)
+        out["cpu_baseline"]["small_case"] = oracle_small_case()
     codec.close()
     print(json.dumps(out))
 
