@@ -327,6 +327,22 @@ def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
     return res
 
 
+def float32_case(codec, torch, reps=10):
+    """The 2 GiB float32 workload (2^29 values: low-precision sinusoid
+    segments, then two interpolated 3-D fields at full precision):
+    device-resident compression and decompression (median kernel time of
+    reps calls) and host -> host through the pipeline, as for the float64
+    workload."""
+    from paper_2511_04140_amd import workloads as W
+    x = W.mixed_f32(1 << 29, seed=3)
+    xd = torch.from_numpy(x).cuda()
+    ratio, c, d = _device_rates(codec, torch, xd, reps)
+    del xd
+    torch.cuda.empty_cache()
+    return {"workload": "mixed_f32: 536,870,912 float32 values (2 GiB)", "ratio": ratio,
+            "compress_gbps": c, "decompress_gbps": d, "host_pipeline": host_pipeline(codec, x, torch)}
+
+
 def codec_bound(x):
     from paper_2511_04140_amd import codec as C
     import torch
@@ -558,6 +574,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 10,000-series batched launch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the ablation-variant measurement")
+    ap.add_argument("--no-float32", action="store_true", help="skip the 2 GiB float32 workload")
     ap.add_argument("--full-range", action="store_true",
                     help="also stream the full-length-range 10,000-series batch (about 109 GB) through the GPU")
     ap.add_argument("--studies", action="store_true",
@@ -682,6 +699,9 @@ def main():
     if not args.no_host:
         out["host_pipeline"] = host_pipeline(codec, x, torch)
         log(f"host pipeline: {out['host_pipeline']}")
+    if not args.no_float32:
+        out["float32"] = float32_case(codec, torch)
+        log(f"float32: {out['float32']}")
     if not args.no_batched:
         out["batched"] = batched(codec, torch)
         torch.cuda.empty_cache()

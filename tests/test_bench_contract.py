@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_sections_exist():
     sys.path.insert(0, ROOT)
     import bench
-    for name in ("cpu_baseline", "host_pipeline", "batched", "serving", "ablation", "studies", "full_range", "measured_traffic",
+    for name in ("cpu_baseline", "host_pipeline", "batched", "serving", "ablation", "float32_case", "oracle_small_case", "studies", "full_range", "measured_traffic",
                  "kernel_source_digest", "main"):
         assert callable(getattr(bench, name)), name
 
