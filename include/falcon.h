@@ -123,7 +123,12 @@ falcon_status falcon_compress_variant(falcon_ctx* ctx, const void* d_in, size_t 
  * row extents inside the chunk's size, sizes summing to the payload byte
  * count): a failure gives FALCON_ERR_CORRUPT_STREAM.  If out_cap_bytes is
  * below N times the element size, FALCON_ERR_BUFFER_TOO_SMALL is returned
- * before any launch and *n_out still receives N. */
+ * before any launch and *n_out still receives N.  d_in must be 4-byte and
+ * d_out element-size aligned (else FALCON_ERR_INVALID_ARG); d_out may sit
+ * at any element offset inside a larger buffer.  Only d_out[0, N) is
+ * written.  On FALCON_ERR_CORRUPT_STREAM the chunks that passed their
+ * checks are written and the failing ones are not, so d_out[0, N) holds no
+ * defined result. */
 falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len, void* d_out,
                                 size_t out_cap_bytes, size_t* n_out, void* stream);
 
