@@ -124,7 +124,7 @@ static int fl10_32(float a) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Alg. 2 DPAndDSCalculation (Sec. 3.2.2)                                    */
+/* Decimal place and significand (Def. 2, Sec. 3.2.2)                        */
 /* ------------------------------------------------------------------------- */
 /* binary64 constants: alpha <= 22 keeps 10^alpha exact (Thm. 3);
  * beta <= 15 is the precision guard of Thm. 2 / Thm. 4. */
@@ -136,69 +136,104 @@ static int fl10_32(float a) {
 #define A_MAX32 10
 #define B_MAX32 6
 
-/* Result of Alg. 2 for one value.  exc = 1 marks the exception outcome; every
- * exception is reported as (A_MAX+1, B_MAX+1) (reading R7). */
+/* Decimal place and decimal significand of one value (Def. 2), found the
+ * way Sec. 3.2.2 finds them: scale the value by growing powers of ten until
+ * the product is an integer within the error bound of Thm. 4, then make sure
+ * that integer divides back to the same value.  The result is (alpha, beta,
+ * exc); exc = 1 marks a value the digit transformation cannot take, reported
+ * as (A_MAX+1, B_MAX+1) whatever made it fail (reading R7). */
 typedef struct { int alpha, beta, exc; } dpds_t;
 
+static dpds_t dpds_exception(int a_max, int b_max) {
+  dpds_t e = {a_max + 1, b_max + 1, 1};
+  return e;
+}
+
+/* The largest decimal place the search may reach for a value whose
+ * FL10 is fl: beta = alpha + fl + 1 (Eq. 2) must stay within B_MAX, the
+ * precision guard of Thm. 2 / Thm. 4, and 10^alpha must be exact, alpha
+ * within A_MAX (Thm. 3).  Negative when no place is allowed. */
+static int place_limit(int fl, int a_max, int b_max) {
+  int lim = b_max - 1 - fl;
+  return lim < a_max ? lim : a_max;
+}
+
+/* binary64 ------------------------------------------------------------------ */
+/* Does the search stop at place alpha?  x = v (x) 10^alpha, one rounded
+ * product (the machine multiply of Sec. 1).  Thm. 4: x stands for an
+ * integer when it lies within |x| * 2^-52 of its nearest integer (round =
+ * rint, reading R5).  Fal_Elf's rule (Sec. 1): only where x is an exact
+ * integer.  The nearest integer is handed back in *r. */
+static int stops_at_64(double v, int alpha, int elf, double* r) {
+  const double x = v * pow10_64(alpha);
+  *r = rint(x);
+  if (elf) return x == floor(x);
+  return fabs(x - *r) <= fabs(x) * 0x1p-52;
+}
+
+/* Exactness guard of Alg. 2: the integer, divided by 10^alpha with IEEE
+ * division (correctly rounded), must give back v bit for bit. */
+static int recovers_64(double v, double r, int alpha) {
+  return bits64(r / pow10_64(alpha)) == bits64(v);
+}
+
+/* The first place in [0, lim] where the search stops, or -1. */
+static int first_stop_64(double v, int lim, int elf, double* r) {
+  for (int alpha = 0; alpha <= lim; ++alpha)
+    if (stops_at_64(v, alpha, elf, r)) return alpha;
+  return -1;
+}
+
 static dpds_t dpds_f64(double v, int elf) {
-  dpds_t res;
-  uint64_t b = bits64(v);
-  /* Special case of Alg. 2: v = 0.  Sec. 2.1 defines v = 0 as "all 64 bits
-   * zero", so only +0.0 takes it (reading R2); -0.0 falls to the exception
-   * route, which keeps its sign bit through BinLong. */
-  if (b == 0) { res.alpha = 0; res.beta = 0; res.exc = 0; return res; }
-  unsigned ef = (unsigned)((b >> 52) & 0x7FF);
-  if (ef == 0 || ef == 0x7FF) { /* -0.0, subnormal, Inf, NaN: reading R3 */
-    res.alpha = A_MAX64 + 1; res.beta = B_MAX64 + 1; res.exc = 1; return res;
+  const uint64_t b = bits64(v);
+  /* Alg. 2's special case v = 0 is taken only by +0.0, the all-zero bit
+   * pattern of Sec. 2.1 (reading R2); -0.0 keeps its sign through Case 2. */
+  if (b == 0) {
+    dpds_t z = {0, 0, 0};
+    return z;
   }
-  int alpha = 0;
-  int beta = alpha + fl10_64(fabs(v)) + 1; /* Eq. 2 */
-  while (beta <= B_MAX64 && alpha <= A_MAX64) {
-    double x = v * pow10_64(alpha);        /* v (x) 10^alpha, one rounding */
-    double r = rint(x);                    /* round (ties-to-even, R5) */
-    double eps = fabs(x - r);
-    double mu = fabs(x) * 0x1p-52;         /* |v (x) 10^alpha| * 2^-52 */
-    /* Thm. 4 stopping rule; Fal_Elf stops only where the product is an
-     * exact integer (x equal to its floor, Sec. 1) */
-    if (elf ? x == floor(x) : eps <= mu) {
-      double back = r / pow10_64(alpha);   /* correctly rounded divide */
-      if (bits64(back) != b) break;        /* recover check fails -> exception */
-      res.alpha = alpha; res.beta = beta; res.exc = 0;
-      return res;
-    }
-    alpha += 1;
-    beta += 1;
-  }
-  res.alpha = A_MAX64 + 1; res.beta = B_MAX64 + 1; res.exc = 1;
-  return res;
+  const unsigned ef = (unsigned)((b >> 52) & 0x7FF);
+  if (ef == 0 || ef == 0x7FF) return dpds_exception(A_MAX64, B_MAX64); /* R3 */
+  const int fl = fl10_64(fabs(v));
+  double r = 0.0;
+  const int alpha = first_stop_64(v, place_limit(fl, A_MAX64, B_MAX64), elf, &r);
+  if (alpha < 0 || !recovers_64(v, r, alpha)) return dpds_exception(A_MAX64, B_MAX64);
+  dpds_t d = {alpha, alpha + fl + 1, 0}; /* Eq. 2 */
+  return d;
+}
+
+/* binary32: the same steps in binary32 arithmetic, bound 2^-23 ---------------- */
+static int stops_at_32(float v, int alpha, int elf, float* r) {
+  const float x = v * pow10_32(alpha);
+  *r = rintf(x);
+  if (elf) return x == floorf(x);
+  return fabsf(x - *r) <= fabsf(x) * 0x1p-23f;
+}
+
+static int recovers_32(float v, float r, int alpha) {
+  return bits32(r / pow10_32(alpha)) == bits32(v);
+}
+
+static int first_stop_32(float v, int lim, int elf, float* r) {
+  for (int alpha = 0; alpha <= lim; ++alpha)
+    if (stops_at_32(v, alpha, elf, r)) return alpha;
+  return -1;
 }
 
 static dpds_t dpds_f32(float v, int elf) {
-  dpds_t res;
-  uint32_t b = bits32(v);
-  if (b == 0) { res.alpha = 0; res.beta = 0; res.exc = 0; return res; }
-  unsigned ef = (b >> 23) & 0xFF;
-  if (ef == 0 || ef == 0xFF) {
-    res.alpha = A_MAX32 + 1; res.beta = B_MAX32 + 1; res.exc = 1; return res;
+  const uint32_t b = bits32(v);
+  if (b == 0) {
+    dpds_t z = {0, 0, 0};
+    return z;
   }
-  int alpha = 0;
-  int beta = alpha + fl10_32(fabsf(v)) + 1;
-  while (beta <= B_MAX32 && alpha <= A_MAX32) {
-    float x = v * pow10_32(alpha);
-    float r = rintf(x);
-    float eps = fabsf(x - r);
-    float mu = fabsf(x) * 0x1p-23f;
-    if (elf ? x == floorf(x) : eps <= mu) {
-      float back = r / pow10_32(alpha);
-      if (bits32(back) != b) break;
-      res.alpha = alpha; res.beta = beta; res.exc = 0;
-      return res;
-    }
-    alpha += 1;
-    beta += 1;
-  }
-  res.alpha = A_MAX32 + 1; res.beta = B_MAX32 + 1; res.exc = 1;
-  return res;
+  const unsigned ef = (b >> 23) & 0xFF;
+  if (ef == 0 || ef == 0xFF) return dpds_exception(A_MAX32, B_MAX32);
+  const int fl = fl10_32(fabsf(v));
+  float r = 0.0f;
+  const int alpha = first_stop_32(v, place_limit(fl, A_MAX32, B_MAX32), elf, &r);
+  if (alpha < 0 || !recovers_32(v, r, alpha)) return dpds_exception(A_MAX32, B_MAX32);
+  dpds_t d = {alpha, alpha + fl + 1, 0};
+  return d;
 }
 
 /* ------------------------------------------------------------------------- */
