@@ -25,12 +25,25 @@
  * Conventions for every entry point:
  *   - Pointers named d_* are device pointers (HIP device memory of the
  *     context's device); h_* are host pointers.  The caller owns every
- *     buffer; the library keeps no caller pointer after the call returns.
+ *     buffer.
  *   - Input arrays must be aligned to their element size; output streams
  *     to 4 bytes.
- *   - Every call is synchronous with respect to the host: it enqueues its
- *     kernels on `stream` (a hipStream_t; NULL selects the context's own
- *     stream), waits for them, and only then writes its host outputs.
+ *   - The device-resident calls (falcon_compress, falcon_compress_variant,
+ *     falcon_decompress, falcon_decompress_n and the *_each loops) are
+ *     asynchronous on `stream` (a hipStream_t; NULL selects the context's
+ *     own stream): they check their arguments, enqueue their kernels and
+ *     return.  The caller keeps its buffers (and host length pointers)
+ *     valid until the work is done: until falcon_sync returns, or until the
+ *     stream has passed the call.  Lengths that only the device knows (the
+ *     stream length of a compression) reach host memory at falcon_sync;
+ *     with FALCON_OPT_DEVICE_LENGTHS they are written in stream order to
+ *     device memory instead.  Errors found on the device (a corrupt stream)
+ *     are reported by falcon_sync.  With FALCON_OPT_BLOCKING every device
+ *     call synchronises itself and reports its own errors.
+ *   - Successive device calls on one context are ordered even when they use
+ *     different streams (they share the context's scratch): a call on a new
+ *     stream first waits for the previous call.
+ *   - The host <-> host calls, batch calls and plan runs are synchronous.
  *   - Errors are reported as status codes; nothing unwinds across the ABI.
  *     On any error the contents of output buffers are unspecified.
  *   - A context is used by one host thread at a time; distinct contexts are
@@ -59,11 +72,52 @@ typedef enum {
 
 typedef struct falcon_ctx falcon_ctx;
 
-/* Creates a context on HIP device `device`: a stream, pinned staging and
- * device scratch (per-chunk metadata, sizes and offsets for the prefix sum,
- * an error word), grown on demand.
- * Returns FALCON_ERR_DEVICE if the device cannot be used. */
-falcon_status falcon_create(int device, falcon_ctx** out);
+/* How falcon_compress runs on the device (both give the same stream).
+ *  TWO_PASS     a size pass computes every chunk's size (Sec. 3.3), a prefix
+ *               scan turns the sizes into offsets (Sec. 3.4), and a write
+ *               pass recomputes each chunk and writes it at its offset; no
+ *               chunk waits for another.  The default.
+ *  SINGLE_PASS  one launch: waves take chunks from a work queue (atomic
+ *               ticket counters) and each chunk finds its offset with a
+ *               decoupled look-back over the sizes published by the chunks
+ *               before it (the synchronisation of Sec. 3.4), so the input
+ *               is read once. */
+typedef enum falcon_compress_form {
+  FALCON_FORM_TWO_PASS = 0,
+  FALCON_FORM_SINGLE_PASS = 1
+} falcon_compress_form;
+
+/* Context options.  A zero-initialised struct, or opts = NULL, gives the
+ * defaults: asynchronous device calls, host length pointers, two passes. */
+typedef struct falcon_opts {
+  unsigned flags;     /* FALCON_OPT_* */
+  int compress_form;  /* falcon_compress_form of falcon_compress */
+} falcon_opts;
+
+enum {
+  /* every device call waits for its own work, writes its host outputs and
+   * reports its own errors before returning */
+  FALCON_OPT_BLOCKING = 1,
+  /* out_len (falcon_compress, falcon_compress_variant) is a device pointer
+   * to a size_t that the kernels write in stream order */
+  FALCON_OPT_DEVICE_LENGTHS = 2
+};
+
+/* Creates a context on HIP device `device` with options opts (NULL: the
+ * defaults): a stream, pinned staging and device scratch (per-chunk
+ * metadata, sizes and offsets for the prefix sum, work-queue counters and
+ * status words, an error word), grown on demand.  Returns
+ * FALCON_ERR_INVALID_ARG for unknown option bits or form, FALCON_ERR_DEVICE
+ * if the device cannot be used. */
+falcon_status falcon_create(int device, const falcon_opts* opts, falcon_ctx** out);
+
+/* Waits for the work of every device call made on ctx since the last
+ * falcon_sync, writes the host lengths those calls left pending, and
+ * returns the first error the device found among them: FALCON_ERR_CORRUPT_STREAM
+ * when a decompressed chunk failed a check, FALCON_ERR_DEVICE when a HIP call
+ * failed or a single-pass look-back gave up (which a correct run never
+ * does).  FALCON_OK otherwise, also when there was nothing to wait for. */
+falcon_status falcon_sync(falcon_ctx* ctx);
 
 /* Releases everything the context owns.  NULL is ignored. */
 void falcon_destroy(falcon_ctx* ctx);
@@ -76,10 +130,12 @@ size_t falcon_compress_bound(size_t n, falcon_dtype dt);
 
 /* Compresses n values at d_in (device) into d_out (device, out_cap bytes).
  * Sec. 3.2-3.5 and Alg. 3: per-chunk integer conversion and adaptive
- * bit-plane encoding; the chunk sizes (Sec. 3.4) come from a first pass over
- * the input, a prefix sum turns them into offsets, and a second pass writes
- * every chunk at its offset.  *out_len (host) receives the stream
- * length.  Returns FALCON_ERR_BUFFER_TOO_SMALL without launching anything if
+ * bit-plane encoding, the chunks packed by a prefix sum of their sizes
+ * (Sec. 3.4), in the context's falcon_compress_form.  Asynchronous: *out_len
+ * receives the stream length at falcon_sync (a host size_t), or in stream
+ * order with FALCON_OPT_DEVICE_LENGTHS (a device size_t); the stream header
+ * at d_out + 24 also holds the payload byte count once the work is done.
+ * Returns FALCON_ERR_BUFFER_TOO_SMALL without launching anything if
  * out_cap < falcon_compress_bound(n, dt).  n = 0 gives a 32-byte stream. */
 falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt,
                               void* d_out, size_t out_cap, size_t* out_len, void* stream);
@@ -117,20 +173,34 @@ falcon_status falcon_compress_variant(falcon_ctx* ctx, const void* d_in, size_t 
 
 /* Decompresses the stream of in_len bytes at d_in (device) into d_out
  * (device, out_cap_bytes bytes).  Sec. 4: scan of the size array into chunk
- * offsets, per-chunk bit-plane decoding, inverse of Eq. 4 and Eq. 3.
- * *n_out (host) receives the value count N.  The header is checked on the
- * host (one 32-byte copy); every chunk is checked on the device (bit width,
- * row extents inside the chunk's size, sizes summing to the payload byte
- * count): a failure gives FALCON_ERR_CORRUPT_STREAM.  If out_cap_bytes is
+ * offsets, per-chunk bit-plane decoding, inverse of Eq. 4 and Eq. 3.  The
+ * value count and dtype come from the stream header, which this call reads
+ * to the host (one 32-byte copy that waits for the work already on `stream`)
+ * and checks; *n_out (host) receives N before the call returns.  The
+ * decoding is then enqueued as by falcon_decompress_n.  If out_cap_bytes is
  * below N times the element size, FALCON_ERR_BUFFER_TOO_SMALL is returned
  * before any launch and *n_out still receives N.  d_in must be 4-byte and
  * d_out element-size aligned (else FALCON_ERR_INVALID_ARG); d_out may sit
  * at any element offset inside a larger buffer.  Only d_out[0, N) is
- * written.  On FALCON_ERR_CORRUPT_STREAM the chunks that passed their
- * checks are written and the failing ones are not, so d_out[0, N) holds no
- * defined result. */
+ * written. */
 falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len, void* d_out,
                                 size_t out_cap_bytes, size_t* n_out, void* stream);
+
+/* Decompresses a stream that the caller knows to hold n values of type dt
+ * (the count and dtype it compressed, or falcon_stream_info of its header)
+ * without any host access to the stream: fully asynchronous.  The header is
+ * checked on the device against n, dt and in_len, and every chunk is
+ * checked (bit width, row extents inside the chunk's size, sizes summing to
+ * the payload byte count); a failure is reported as
+ * FALCON_ERR_CORRUPT_STREAM by falcon_sync (or at once with
+ * FALCON_OPT_BLOCKING), and then the chunks that passed their checks are
+ * written and the failing ones are not, so d_out[0, n) holds no defined
+ * result.  On the host: FALCON_ERR_CORRUPT_STREAM if in_len cannot hold the
+ * header and n chunk sizes, FALCON_ERR_BUFFER_TOO_SMALL if out_cap_bytes <
+ * n times the element size, FALCON_ERR_INVALID_ARG for a null or misaligned
+ * pointer or an unknown dtype; nothing is launched then. */
+falcon_status falcon_decompress_n(falcon_ctx* ctx, const void* d_in, size_t in_len, size_t n, falcon_dtype dt,
+                                  void* d_out, size_t out_cap_bytes, void* stream);
 
 /* Host -> host compression through the asynchronous pipeline of Sec. 3.1
  * (Alg. 1, event-driven scheduler).  The n values at h_in (host) are cut
@@ -227,6 +297,17 @@ typedef struct falcon_plan_info {
   int graph;            /* 1 if runs replay a HIP graph */
   uint64_t total_chunks;
 } falcon_plan_info;
+
+/* The one-series-per-launch path over count series, as a C loop: one
+ * asynchronous falcon_compress (falcon_decompress_each: falcon_decompress_n)
+ * per series, in order, on `stream`, each with its own launches; the stream
+ * lengths are written by the kernels to device memory and read back once,
+ * after a single wait at the end (s[i].out_len; decompression: s[i].n).
+ * Descriptors as for the batch calls below, checked on the host before any
+ * launch.  It is the baseline that batch calls and plans are measured
+ * against. */
+falcon_status falcon_compress_each(falcon_ctx* ctx, falcon_series* s, size_t count, void* stream);
+falcon_status falcon_decompress_each(falcon_ctx* ctx, falcon_series* s, size_t count, void* stream);
 
 /* Compresses count series in one launch sequence (no tuning, no graph):
  * every chunk of every series is a work item of the same size pass, one
@@ -328,15 +409,18 @@ void falcon_server_destroy(falcon_server* s);
  * a version-1 Falcon header. */
 falcon_status falcon_stream_info(const void* h_hdr, size_t len, size_t* n, falcon_dtype* dt);
 
-/* Device time in milliseconds of the last falcon_compress (its three
- * stages: size pass, scan of the sizes, write pass) or falcon_decompress
- * (its decoding kernel, after the scan of the size array), measured with
- * HIP events recorded on the launch stream.  Intended for roofline
- * accounting; FALCON_ERR_INVALID_ARG if no call has run yet. */
+/* Device time in milliseconds of the last falcon_compress /
+ * falcon_compress_variant (all its launches: size pass, scan, write pass; or
+ * the single-pass launch and the clearing of its counters) or
+ * falcon_decompress / falcon_decompress_n (the scan of the size array and
+ * the decoding kernel), measured with HIP events recorded on the launch
+ * stream; waits for that call's work.  Intended for roofline accounting;
+ * FALCON_ERR_INVALID_ARG if no call has run yet. */
 falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms);
 
-/* The stages of that call separately, ms[0..2]: compression size pass,
- * scan, write pass; decompression 0, scan, decoding kernel. */
+/* The stages of that call separately, ms[0..2]: two-pass compression: size
+ * pass, scan, write pass; single-pass compression: the whole launch, 0, 0;
+ * decompression: 0, scan, decoding kernel. */
 falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms);
 
 /* Static, human-readable name of a status code. */

@@ -44,6 +44,16 @@ class PlanInfo(ctypes.Structure):
                 ("graph", ctypes.c_int), ("total_chunks", ctypes.c_uint64)]
 
 
+class Opts(ctypes.Structure):
+    """falcon_opts of falcon.h."""
+    _fields_ = [("flags", ctypes.c_uint), ("compress_form", ctypes.c_int)]
+
+
+OPT_BLOCKING = 1
+OPT_DEVICE_LENGTHS = 2
+FORMS = {"two_pass": 0, "single_pass": 1}
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("pool", ctypes.c_void_p), ("lanes", ctypes.c_int),
                 ("max_batch", ctypes.c_int)]
@@ -76,8 +86,12 @@ def _load():
             "(python -c 'import __graft_entry__ as g; g.build()')")
     L = ctypes.CDLL(lib_path)
     vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
-    L.falcon_create.argtypes = [i, ctypes.POINTER(vp)]
+    L.falcon_create.argtypes = [i, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
     L.falcon_create.restype = i
+    L.falcon_sync.argtypes = [vp]
+    L.falcon_sync.restype = i
+    L.falcon_decompress_n.argtypes = [vp, vp, sz, sz, i, vp, sz, vp]
+    L.falcon_decompress_n.restype = i
     L.falcon_destroy.argtypes = [vp]
     L.falcon_destroy.restype = None
     L.falcon_compress_bound.argtypes = [sz, i]
@@ -105,6 +119,10 @@ def _load():
     L.falcon_set_pipeline_scheduler.argtypes = [vp, i]
     L.falcon_set_pipeline_scheduler.restype = i
     ps = ctypes.POINTER(Series)
+    L.falcon_compress_each.argtypes = [vp, ps, sz, vp]
+    L.falcon_compress_each.restype = i
+    L.falcon_decompress_each.argtypes = [vp, ps, sz, vp]
+    L.falcon_decompress_each.restype = i
     L.falcon_compress_batch.argtypes = [vp, ps, sz, vp]
     L.falcon_compress_batch.restype = i
     L.falcon_decompress_batch.argtypes = [vp, ps, sz, vp]
@@ -163,15 +181,25 @@ def _stream_handle(device: torch.device):
 
 
 class Codec:
-    """One library context on one GPU (a stream, pinned staging, scratch)."""
+    """One library context on one GPU (a stream, pinned staging, scratch).
 
-    def __init__(self, device: int | torch.device = 0):
+    blocking=True (the default here) makes every device call wait for its
+    work and report its own errors, as the methods below expect; with
+    blocking=False the *_async methods enqueue and sync() completes them.
+    form selects how compression runs ("two_pass" or "single_pass")."""
+
+    def __init__(self, device: int | torch.device = 0, blocking: bool = True, form: str = "two_pass",
+                 device_lengths: bool = False):
         dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.device = dev
+        self.blocking = blocking
+        self.device_lengths = device_lengths
         self._ctx = ctypes.c_void_p()
-        st = lib().falcon_create(dev.index or 0, ctypes.byref(self._ctx))
+        opts = Opts((OPT_BLOCKING if blocking else 0) | (OPT_DEVICE_LENGTHS if device_lengths else 0), FORMS[form])
+        st = lib().falcon_create(dev.index or 0, ctypes.byref(opts), ctypes.byref(self._ctx))
         if st != 0:
             raise FalconError(st, "falcon_create")
+        self._pending = []
 
     def close(self):
         if self._ctx:
@@ -201,9 +229,61 @@ class Codec:
             raise FalconError(st, "falcon_last_stage_ms")
         return [ms[0], ms[1], ms[2]]
 
+    def sync(self):
+        """falcon_sync: waits for the asynchronous calls made since the last
+        sync; raises FalconError for an error the device found among them."""
+        st = lib().falcon_sync(self._ctx)
+        self._pending = []
+        if st != 0:
+            raise FalconError(st, "falcon_sync")
+
+    def compress_async(self, x: torch.Tensor, out: torch.Tensor, out_len=None, stream=None):
+        """Enqueues falcon_compress of x into out (a uint8 device tensor of at
+        least compress_bound bytes).  Returns the length holder: a
+        ctypes.c_size_t filled at sync(), or, on a device_lengths codec, the
+        int64 device tensor out_len (one element) that the kernels fill."""
+        code = _dtype_code(x.dtype)
+        n = x.numel()
+        if self.device_lengths:
+            holder = out_len
+            ptr = ctypes.cast(ctypes.c_void_p(out_len.data_ptr()), ctypes.POINTER(ctypes.c_size_t))
+        else:
+            holder = ctypes.c_size_t()
+            ptr = ctypes.byref(holder)
+            self._pending.append(holder)
+        h = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(x.device)
+        st = lib().falcon_compress(self._ctx, ctypes.c_void_p(x.data_ptr() if n else 0), n, code,
+                                   ctypes.c_void_p(out.data_ptr()), out.numel(), ptr, h)
+        if st != 0:
+            raise FalconError(st, "falcon_compress")
+        return holder
+
+    def decompress_n_async(self, stream_bytes: torch.Tensor, n: int, dtype: torch.dtype, out: torch.Tensor,
+                           stream=None):
+        """Enqueues falcon_decompress_n: the stream in stream_bytes holds n
+        values of dtype; they go to out.  No host access to the stream."""
+        h = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(out.device)
+        st = lib().falcon_decompress_n(self._ctx, ctypes.c_void_p(stream_bytes.data_ptr()), stream_bytes.numel(),
+                                       n, _dtype_code(dtype), ctypes.c_void_p(out.data_ptr() if out.numel() else 0),
+                                       out.numel() * out.element_size(), h)
+        if st != 0:
+            raise FalconError(st, "falcon_decompress_n")
+
+    def decompress_n(self, stream_bytes: torch.Tensor, n: int, dtype: torch.dtype,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """falcon_decompress_n (the count and dtype from the caller)."""
+        if out is None:
+            out = torch.empty(n, dtype=dtype, device=stream_bytes.device)
+        self.decompress_n_async(stream_bytes, n, dtype, out)
+        if not self.blocking:
+            self.sync()
+        return out[:n]
+
     def compress(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Compresses a contiguous float32/float64 device tensor; returns the
         stream as a uint8 device tensor (a view of `out` when given)."""
+        if self.device_lengths:
+            raise ValueError("compress() needs a codec with host lengths")
         if not x.is_cuda or not x.is_contiguous():
             raise ValueError("compress needs a contiguous device tensor")
         code = _dtype_code(x.dtype)
@@ -217,6 +297,8 @@ class Codec:
                                    _stream_handle(x.device))
         if st != 0:
             raise FalconError(st, "falcon_compress")
+        if not self.blocking:
+            self.sync()
         return out[: olen.value]
 
     def compress_variant(self, x: torch.Tensor, variant: str, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -236,6 +318,8 @@ class Codec:
                                            _stream_handle(x.device))
         if st != 0:
             raise FalconError(st, "falcon_compress_variant")
+        if not self.blocking:
+            self.sync()
         return out[: olen.value]
 
     def decompress(self, stream: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -260,6 +344,8 @@ class Codec:
                                      _stream_handle(stream.device))
         if st != 0:
             raise FalconError(st, "falcon_decompress")
+        if not self.blocking:
+            self.sync()
         return out[: nout.value]
 
     # -- host -> host through the stream pipeline ---------------------------
@@ -343,6 +429,24 @@ class Codec:
                               o.numel() * o.element_size(), code, 0)
             views.append(o)
         return descs, views
+
+    def compress_each(self, xs, outs=None):
+        """The one-series-per-launch loop (falcon_compress_each): one
+        asynchronous compression per tensor, one wait; returns the streams."""
+        descs, views = self._compress_descs(xs, outs)
+        st = lib().falcon_compress_each(self._ctx, descs, len(xs), _stream_handle(self.device))
+        if st != 0:
+            raise FalconError(st, "falcon_compress_each")
+        return [v[: descs[i].out_len] for i, v in enumerate(views)]
+
+    def decompress_each(self, streams, counts, dtypes, outs=None):
+        """falcon_decompress_each: one asynchronous falcon_decompress_n per
+        stream, one wait."""
+        descs, views = self._decompress_descs(streams, counts, dtypes, outs)
+        st = lib().falcon_decompress_each(self._ctx, descs, len(streams), _stream_handle(self.device))
+        if st != 0:
+            raise FalconError(st, "falcon_decompress_each")
+        return views
 
     def compress_batch(self, xs, outs=None):
         """Compresses a list of float32/float64 device tensors in one launch

@@ -31,6 +31,7 @@ void write_header(uint8_t* h, falcon_dtype dt, uint64_t n, uint64_t payload) {
 falcon_status lane_init(Lane& l) {
   if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc(&l.ctl, 64) != hipSuccess || hipMemset(l.ctl, 0, 64) != hipSuccess ||
+      hipMalloc(&l.qctr, 8 * kQueueGroups * kQueueStride) != hipSuccess ||
       hipHostMalloc(&l.stage, kStageBytes, hipHostMallocDefault) != hipSuccess) {
     lane_free(l);
     return FALCON_ERR_DEVICE;
@@ -45,6 +46,8 @@ void lane_free(Lane& l) {
   if (l.tiles) (void)hipFree(l.tiles);
   if (l.meta) (void)hipFree(l.meta);
   if (l.gsizes) (void)hipFree(l.gsizes);
+  if (l.status) (void)hipFree(l.status);
+  if (l.qctr) (void)hipFree(l.qctr);
   if (l.ctl) (void)hipFree(l.ctl);
   if (l.stage) (void)hipHostFree(l.stage);
   if (l.stream) (void)hipStreamDestroy(l.stream);
@@ -90,48 +93,85 @@ int grid_for(int max_grid, uint64_t nchunks, int waves_per_block) {
 
 }  // namespace
 
-// Two-pass compression: size pass, scan of the sizes, write pass (see
-// codec_kernels.hpp).  The lane's offset array receives the scan.
-falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
-                               hipStream_t s, bool timed, int variant) {
-  const uint64_t nc = chunks_of(n);
-  falcon_status st = prepare_launch(l, nc ? nc : 1, scan_tiles(nc) + 1, s);
-  if (st == FALCON_OK) st = grow_raw(&l.meta, &l.meta_cap, nc ? nc : 1, s);
-  if (st == FALCON_OK) st = grow_raw(&l.gsizes, &l.gsizes_cap, nc ? nc : 1, s);
+// Makes the lane's status array hold nchunks words, picks the tag of the
+// next single-pass launch and clears the ticket counters.  The status array
+// is cleared when it is (re)allocated and whenever the 16-bit tag wraps, so
+// a word left by an earlier launch never carries the current tag.
+falcon_status prepare_queue(Lane& l, uint64_t nchunks, hipStream_t s) {
+  const size_t old_cap = l.status_cap;
+  const uint64_t* old = l.status;
+  falcon_status st = grow_raw(&l.status, &l.status_cap, nchunks, s);
   if (st != FALCON_OK) return st;
+  l.qtag = (l.qtag + 1) & 0xFFFFu;
+  if (l.status != old || l.status_cap != old_cap || l.qtag == 0) {
+    if (l.qtag == 0) l.qtag = 1;
+    if ((st = dev_err(launch_fill_u64(l.status, l.status_cap, 0, s))) != FALCON_OK) return st;
+  }
+  return dev_err(launch_fill_u64(l.qctr, (size_t)kQueueGroups * kQueueStride, 0, s));
+}
+
+// Compression, in one of two forms.  Two passes (the default, and the
+// only form of the ablation variants): a size pass, a scan of the chunk
+// sizes into offsets, a write pass that redoes a4-a7 and writes each chunk
+// at its offset.  Single pass: one launch in which waves take chunks from
+// a work queue and find their offsets with a decoupled look-back (see
+// codec_kernels.hpp).  Both give the same stream.
+falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
+                               hipStream_t s, bool timed, int variant, int form, uint64_t* d_len) {
+  const uint64_t nc = chunks_of(n);
+  falcon_status st = FALCON_OK;
   CompressArgs a{};
   a.one.in = d_in;
   a.one.out = static_cast<uint8_t*>(d_out);
   a.one.n = n;
   a.one.chunk0 = 0;
   a.one.dtype = (uint32_t)dt;
+  a.one.idx = 0;
   a.many = nullptr;
   a.nseries = 1;
   a.total_chunks = nc;
-  a.lens = nullptr;
-  a.meta = l.meta;
-  a.gsizes = l.gsizes;
-  a.offsets = l.offsets;
+  a.lens = d_len;
   a.relative = 0;
-  const int nw = variant ? kVariantWaves : kCompressWaves;
-  const int g1 = grid_for(variant ? ctx->grid_v[dt][variant][1] : max_grid_c(ctx, dt, 1, nw), nc, nw);
-  const int g2 = grid_for(variant ? ctx->grid_v[dt][variant][2] : max_grid_c(ctx, dt, 2, nw), nc, nw);
-  auto launch = [&](int pass, int grid) {
-    a.total_waves = (uint32_t)(grid * nw);
-    return dev_err(variant ? launch_compress_variant(a, (int)dt, variant, pass, grid, s)
-                           : launch_compress(a, (int)dt, pass, nw, grid, s));
-  };
   auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
   if (timed) ctx->timed = false;
-  if ((st = mark(0)) != FALCON_OK) return st;
-  if (nc && (st = launch(1, g1)) != FALCON_OK) return st;
-  if ((st = mark(1)) != FALCON_OK) return st;
-  if (nc && (st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch, s))) !=
-                FALCON_OK)
-    return st;
-  if ((st = mark(2)) != FALCON_OK) return st;
-  if ((st = launch(2, g2)) != FALCON_OK) return st;
-  if ((st = mark(3)) != FALCON_OK) return st;
+  if (variant == 0 && form == FALCON_FORM_SINGLE_PASS) {
+    if ((st = mark(0)) != FALCON_OK || (st = prepare_queue(l, nc ? nc : 1, s)) != FALCON_OK) return st;
+    const int nw = kCompressWaves;
+    const int grid = grid_for(max_grid_q(ctx, dt, nw), nc, nw);
+    a.total_waves = (uint32_t)(grid * nw);
+    a.status = l.status;
+    a.qctr = l.qctr;
+    a.qgroups = (uint32_t)(grid < kQueueGroups ? grid : kQueueGroups);
+    a.ctl = l.ctl;
+    a.qtag = l.qtag;
+    if ((st = dev_err(launch_compress_queue(a, (int)dt, nw, grid, s))) != FALCON_OK) return st;
+    if ((st = mark(1)) != FALCON_OK || (st = mark(2)) != FALCON_OK || (st = mark(3)) != FALCON_OK) return st;
+  } else {
+    st = prepare_launch(l, nc ? nc : 1, scan_tiles(nc) + 1, s);
+    if (st == FALCON_OK) st = grow_raw(&l.meta, &l.meta_cap, nc ? nc : 1, s);
+    if (st == FALCON_OK) st = grow_raw(&l.gsizes, &l.gsizes_cap, nc ? nc : 1, s);
+    if (st != FALCON_OK) return st;
+    a.meta = l.meta;
+    a.gsizes = l.gsizes;
+    a.offsets = l.offsets;
+    const int nw = variant ? kVariantWaves : kCompressWaves;
+    const int g1 = grid_for(variant ? ctx->grid_v[dt][variant][1] : max_grid_c(ctx, dt, 1, nw), nc, nw);
+    const int g2 = grid_for(variant ? ctx->grid_v[dt][variant][2] : max_grid_c(ctx, dt, 2, nw), nc, nw);
+    auto launch = [&](int pass, int grid) {
+      a.total_waves = (uint32_t)(grid * nw);
+      return dev_err(variant ? launch_compress_variant(a, (int)dt, variant, pass, grid, s)
+                             : launch_compress(a, (int)dt, pass, nw, grid, s));
+    };
+    if ((st = mark(0)) != FALCON_OK) return st;
+    if (nc && (st = launch(1, g1)) != FALCON_OK) return st;
+    if ((st = mark(1)) != FALCON_OK) return st;
+    if (nc && (st = dev_err(launch_scan_sizes(l.gsizes, nc, 0, ~0u, ~0ull, l.tiles, l.offsets, l.ctl, l.epoch,
+                                              s))) != FALCON_OK)
+      return st;
+    if ((st = mark(2)) != FALCON_OK) return st;
+    if ((st = launch(2, g2)) != FALCON_OK) return st;
+    if ((st = mark(3)) != FALCON_OK) return st;
+  }
   if (timed) {
     ctx->timed = true;
     ctx->timed_compress = true;
@@ -139,20 +179,23 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   return FALCON_OK;
 }
 
-falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t n, falcon_dtype dt,
-                                 uint64_t payload, void* d_out, hipStream_t s, bool timed) {
+falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t in_len, uint64_t n,
+                                 falcon_dtype dt, uint64_t payload, void* d_out, hipStream_t s, bool timed,
+                                 bool copy_error) {
   const uint64_t nc = chunks_of(n);
   falcon_status st = prepare_launch(l, nc, scan_tiles(nc) + 1, s);
   if (st != FALCON_OK) return st;
   // chunk offsets: exclusive prefix of the size array (which the scan also
-  // checks: every size in [lo, hi], their sum equal to the payload bytes).
+  // checks: every size in [lo, hi], and their sum equal to the payload byte
+  // count when the host knows it; otherwise the last chunk's check does that)
   const uint32_t lo = dt == FALCON_FLOAT64 ? 11u : 7u;
   const uint32_t hi = (uint32_t)max_chunk_bytes(dt);
   auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
   if (timed) ctx->timed = false;
   if ((st = mark(0)) != FALCON_OK || (st = mark(1)) != FALCON_OK) return st;
-  if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi, payload, l.tiles,
-                                      l.offsets, l.ctl, l.epoch, s))) != FALCON_OK)
+  if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi,
+                                      payload == kPayloadFromHeader ? ~0ull : payload, l.tiles, l.offsets, l.ctl,
+                                      l.epoch, s))) != FALCON_OK)
     return st;
   DecompressArgs a{};
   a.one.in = d_in;
@@ -160,6 +203,7 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   a.one.n = n;
   a.one.chunk0 = 0;
   a.one.payload_bytes = payload;
+  a.one.in_len = in_len;
   a.one.dtype = (uint32_t)dt;
   a.many = nullptr;
   a.nseries = 1;
@@ -177,8 +221,61 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
     ctx->timed = true;
     ctx->timed_compress = false;
   }
+  if (!copy_error) return FALCON_OK;
   return dev_err(hipMemcpyAsync(l.stage + 32, &l.ctl->error, 4, hipMemcpyDeviceToHost, s));
 }
+
+namespace {
+
+// ---- asynchronous device calls --------------------------------------------
+// A device call runs in three steps: begin_call (stream choice, ordering
+// after the previous call), the enqueue, end_call (records the call's end,
+// and with FALCON_OPT_BLOCKING synchronises and reports at once).
+
+hipStream_t call_stream(falcon_ctx* ctx, void* stream) {
+  return stream ? static_cast<hipStream_t>(stream) : ctx->main.stream;
+}
+
+falcon_status begin_call(falcon_ctx* ctx, hipStream_t s) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
+  if (ctx->last_stream && ctx->last_stream != s && hipStreamWaitEvent(s, ctx->ev_done, 0) != hipSuccess)
+    return FALCON_ERR_DEVICE;
+  return FALCON_OK;
+}
+
+falcon_status end_call(falcon_ctx* ctx, hipStream_t s, falcon_status st) {
+  // the work enqueued so far is recorded even after an error, so that a
+  // later call or falcon_sync still orders after it
+  if (hipEventRecord(ctx->ev_done, s) != hipSuccess && st == FALCON_OK) st = FALCON_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->unsynced = true;
+  if (ctx->opt_flags & FALCON_OPT_BLOCKING) {
+    const falcon_status sy = falcon_sync(ctx);
+    if (st == FALCON_OK) st = sy;
+  }
+  return st;
+}
+
+// A device word that the kernels of one compression fill with its stream
+// length, reported to *dst at falcon_sync.
+falcon_status pending_length(falcon_ctx* ctx, size_t* dst, uint64_t** d_len) {
+  const size_t slot = ctx->pending.size();
+  const size_t b = slot / kLenBlock;
+  if (b == ctx->len_blocks.size()) {
+    void* p = nullptr;
+    if (hipMalloc(&p, kLenBlock * 8) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
+    ctx->len_blocks.push_back(static_cast<uint64_t*>(p));
+  }
+  *d_len = ctx->len_blocks[b] + slot % kLenBlock;
+  ctx->pending.push_back({dst, slot});
+  return FALCON_OK;
+}
+
+// Writes 32 (the stream length of n = 0, which no kernel writes) to a
+// device length word.
+falcon_status empty_length(uint64_t* d_len, hipStream_t s) { return dev_err(launch_fill_u64(d_len, 1, 32, s)); }
+
+}  // namespace
 
 }  // namespace falcon_host
 
@@ -204,33 +301,92 @@ size_t falcon_compress_bound(size_t n, falcon_dtype dt) {
   return 32 + chunks_of(n) * (4 + per);
 }
 
-falcon_status falcon_create(int device, falcon_ctx** out) {
+falcon_status falcon_create(int device, const falcon_opts* opts, falcon_ctx** out) {
   if (!out) return FALCON_ERR_INVALID_ARG;
   *out = nullptr;
+  const unsigned flags = opts ? opts->flags : 0u;
+  const int form = opts ? opts->compress_form : 0;
+  if ((flags & ~(unsigned)(FALCON_OPT_BLOCKING | FALCON_OPT_DEVICE_LENGTHS)) ||
+      (form != FALCON_FORM_TWO_PASS && form != FALCON_FORM_SINGLE_PASS))
+    return FALCON_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FALCON_ERR_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return FALCON_ERR_DEVICE;
   falcon_ctx* ctx = new (std::nothrow) falcon_ctx();
   if (!ctx) return FALCON_ERR_OUT_OF_MEMORY;
   ctx->device = device;
+  ctx->opt_flags = flags;
+  ctx->compress_form = form;
   if (lane_init(ctx->main) != FALCON_OK || hipEventCreate(&ctx->ev[0]) != hipSuccess ||
       hipEventCreate(&ctx->ev[1]) != hipSuccess || hipEventCreate(&ctx->ev[2]) != hipSuccess ||
-      hipEventCreate(&ctx->ev[3]) != hipSuccess) {
+      hipEventCreate(&ctx->ev[3]) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) != hipSuccess) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
-  for (int form = 1; form <= 3; ++form) {
+  for (int form_ = 1; form_ <= 3; ++form_) {
     for (int pass = 1; pass <= 2; ++pass) {
-      ctx->grid_c[form][pass][0] = max_grid_compress(device, form, pass, 8);
-      ctx->grid_c[form][pass][1] = max_grid_compress(device, form, pass, 16);
+      ctx->grid_c[form_][pass][0] = max_grid_compress(device, form_, pass, 8);
+      ctx->grid_c[form_][pass][1] = max_grid_compress(device, form_, pass, 16);
     }
-    ctx->grid_d[form] = max_grid_decompress(device, form);
+    ctx->grid_d[form_] = max_grid_decompress(device, form_);
+    ctx->grid_q[form_][0] = max_grid_compress_queue(device, form_, 8);
+    ctx->grid_q[form_][1] = max_grid_compress_queue(device, form_, 16);
   }
-  for (int form = 1; form <= 2; ++form)
+  for (int f = 1; f <= 2; ++f)
     for (int v = 1; v <= 3; ++v)
-      for (int pass = 1; pass <= 2; ++pass) ctx->grid_v[form][v][pass] = max_grid_compress_variant(device, form, v, pass);
+      for (int pass = 1; pass <= 2; ++pass) ctx->grid_v[f][v][pass] = max_grid_compress_variant(device, f, v, pass);
   *out = ctx;
   return FALCON_OK;
+}
+
+falcon_status falcon_sync(falcon_ctx* ctx) {
+  if (!ctx) return FALCON_ERR_INVALID_ARG;
+  if (!ctx->unsynced) return FALCON_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
+  Lane& l = ctx->main;
+  hipStream_t s = ctx->last_stream;
+  falcon_status st = FALCON_OK;
+  const size_t np = ctx->pending.size();
+  if (np > ctx->len_host_cap) {
+    // grown only here, when no copy into it is in flight
+    if (hipStreamSynchronize(s) != hipSuccess) st = FALCON_ERR_DEVICE;
+    if (ctx->len_host) (void)hipHostFree(ctx->len_host);
+    ctx->len_host = nullptr;
+    ctx->len_host_cap = 0;
+    size_t cap = kLenBlock;
+    while (cap < np) cap *= 2;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, cap * 8, hipHostMallocDefault) != hipSuccess) {
+      st = FALCON_ERR_OUT_OF_MEMORY;
+    } else {
+      ctx->len_host = static_cast<uint64_t*>(p);
+      ctx->len_host_cap = cap;
+    }
+  }
+  for (size_t b = 0; st == FALCON_OK && b * kLenBlock < np; ++b) {
+    const size_t k = np - b * kLenBlock < kLenBlock ? np - b * kLenBlock : kLenBlock;
+    st = dev_err(hipMemcpyAsync(ctx->len_host + b * kLenBlock, ctx->len_blocks[b], k * 8, hipMemcpyDeviceToHost, s));
+  }
+  if (st == FALCON_OK) st = dev_err(hipMemcpyAsync(l.stage + 32, l.ctl, 8, hipMemcpyDeviceToHost, s));
+  const falcon_status sy = dev_err(hipStreamSynchronize(s));
+  if (st == FALCON_OK) st = sy;
+  if (st == FALCON_OK) {
+    for (const auto& p : ctx->pending) *p.dst = (size_t)ctx->len_host[p.slot];
+    // the decompression error word holds the epoch of the last launch whose
+    // chunk failed: a launch since the last sync has a larger one
+    const uint32_t err = rd32(l.stage + 32);
+    if (err != 0 && err > ctx->sync_epoch && err <= l.epoch) st = FALCON_ERR_CORRUPT_STREAM;
+    if (rd32(l.stage + 36) != 0) {
+      (void)launch_fill_u64(reinterpret_cast<uint64_t*>(l.ctl), 1, 0, s);
+      (void)hipStreamSynchronize(s);
+      st = FALCON_ERR_DEVICE;
+    }
+  }
+  ctx->pending.clear();
+  ctx->sync_epoch = l.epoch;
+  ctx->unsynced = false;
+  return st;
 }
 
 void falcon_destroy(falcon_ctx* ctx) {
@@ -238,10 +394,14 @@ void falcon_destroy(falcon_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   pipe_release(ctx);
   if (ctx->main.stream) (void)hipStreamSynchronize(ctx->main.stream);
+  if (ctx->last_stream) (void)hipStreamSynchronize(ctx->last_stream);
   batch_free(ctx->batch);
   lane_free(ctx->main);
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
+  for (uint64_t* b : ctx->len_blocks) (void)hipFree(b);
+  if (ctx->len_host) (void)hipHostFree(ctx->len_host);
   delete ctx;
 }
 
@@ -276,55 +436,121 @@ falcon_status falcon_compress_variant(falcon_ctx* ctx, const void* d_in, size_t 
   const size_t es = elem_size(dt);
   if (es == 0) return FALCON_ERR_INVALID_ARG;
   if (((uintptr_t)d_in % es) || ((uintptr_t)d_out % 4)) return FALCON_ERR_INVALID_ARG;
+  const bool dev_len = (ctx->opt_flags & FALCON_OPT_DEVICE_LENGTHS) != 0;
+  if (dev_len && ((uintptr_t)out_len % 8)) return FALCON_ERR_INVALID_ARG;
   if (out_cap < falcon_compress_bound_variant(n, dt, v)) return FALCON_ERR_BUFFER_TOO_SMALL;
   const uint64_t nc = chunks_of(n);
   if (nc >= 0xFFFFFFF0ull) return FALCON_ERR_INVALID_ARG;
-  if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
-  Lane& l = ctx->main;
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : l.stream;
-  falcon_status st = enqueue_compress(ctx, l, d_in, n, dt, d_out, s, true, (int)v);
+  hipStream_t s = call_stream(ctx, stream);
+  falcon_status st = begin_call(ctx, s);
   if (st != FALCON_OK) return st;
-  if ((st = dev_err(hipMemcpyAsync(l.stage + 40, static_cast<uint8_t*>(d_out) + 24, 8, hipMemcpyDeviceToHost, s))) !=
-      FALCON_OK)
-    return st;
-  if ((st = dev_err(hipStreamSynchronize(s))) != FALCON_OK) return st;
-  *out_len = 32 + 4 * nc + rd64(l.stage + 40);
-  return FALCON_OK;
+  uint64_t* d_len = nullptr;
+  if (dev_len) d_len = reinterpret_cast<uint64_t*>(out_len);
+  else if (n) st = pending_length(ctx, out_len, &d_len);
+  else *out_len = 32;
+  if (st == FALCON_OK)
+    st = enqueue_compress(ctx, ctx->main, d_in, n, dt, d_out, s, true, (int)v, ctx->compress_form, d_len);
+  if (st == FALCON_OK && dev_len && n == 0) st = empty_length(d_len, s);
+  return end_call(ctx, s, st);
+}
+
+falcon_status falcon_decompress_n(falcon_ctx* ctx, const void* d_in, size_t in_len, size_t n, falcon_dtype dt,
+                                  void* d_out, size_t out_cap_bytes, void* stream) {
+  if (!ctx || !d_in || ((uintptr_t)d_in % 4)) return FALCON_ERR_INVALID_ARG;
+  const size_t es = elem_size(dt);
+  if (es == 0) return FALCON_ERR_INVALID_ARG;
+  const uint64_t nc = chunks_of(n);
+  if (nc >= 0xFFFFFFF0ull || in_len < 32 || (in_len - 32) / 4 < nc) return FALCON_ERR_CORRUPT_STREAM;
+  if (out_cap_bytes / es < n) return FALCON_ERR_BUFFER_TOO_SMALL;
+  if (n && (!d_out || ((uintptr_t)d_out % es))) return FALCON_ERR_INVALID_ARG;
+  hipStream_t s = call_stream(ctx, stream);
+  falcon_status st = begin_call(ctx, s);
+  if (st != FALCON_OK) return st;
+  // an empty stream has no chunk to check its header: nothing to launch
+  if (n) st = enqueue_decompress(ctx, ctx->main, static_cast<const uint8_t*>(d_in), in_len, n, dt,
+                                 kPayloadFromHeader, d_out, s, true, false);
+  return end_call(ctx, s, st);
 }
 
 falcon_status falcon_decompress(falcon_ctx* ctx, const void* d_in, size_t in_len, void* d_out, size_t out_cap_bytes,
                                 size_t* n_out, void* stream) {
   if (!ctx || !d_in || !n_out || ((uintptr_t)d_in % 4)) return FALCON_ERR_INVALID_ARG;
   if (in_len < 32) return FALCON_ERR_CORRUPT_STREAM;
-  if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
   Lane& l = ctx->main;
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : l.stream;
-  falcon_status st;
-  if ((st = dev_err(hipMemcpyAsync(l.stage, d_in, 32, hipMemcpyDeviceToHost, s))) != FALCON_OK) return st;
-  if ((st = dev_err(hipStreamSynchronize(s))) != FALCON_OK) return st;
+  hipStream_t s = call_stream(ctx, stream);
+  falcon_status st = begin_call(ctx, s);
+  if (st != FALCON_OK) return st;
+  // the header, read after the work already on the stream
+  if ((st = dev_err(hipMemcpyAsync(l.stage, d_in, 32, hipMemcpyDeviceToHost, s))) != FALCON_OK ||
+      (st = dev_err(hipStreamSynchronize(s))) != FALCON_OK)
+    return end_call(ctx, s, st);
   size_t n = 0;
   falcon_dtype dt;
-  if ((st = falcon_stream_info(l.stage, 32, &n, &dt)) != FALCON_OK) return st;
+  if ((st = falcon_stream_info(l.stage, 32, &n, &dt)) != FALCON_OK) return end_call(ctx, s, st);
   const uint64_t payload = rd64(l.stage + 24);
   const uint64_t nc = chunks_of(n);
-  if (nc >= 0xFFFFFFF0ull || (in_len - 32) / 4 < nc || payload > in_len - 32 - 4 * nc)
-    return FALCON_ERR_CORRUPT_STREAM;
+  if (nc >= 0xFFFFFFF0ull || (in_len - 32) / 4 < nc || payload > in_len - 32 - 4 * nc ||
+      (n == 0 && payload != 0))
+    return end_call(ctx, s, FALCON_ERR_CORRUPT_STREAM);
   *n_out = n;
   const size_t es = elem_size(dt);
-  if (out_cap_bytes / es < n) return FALCON_ERR_BUFFER_TOO_SMALL;
-  if (n == 0) return payload == 0 ? FALCON_OK : FALCON_ERR_CORRUPT_STREAM;
-  if (!d_out || ((uintptr_t)d_out % es)) return FALCON_ERR_INVALID_ARG;
-  if ((st = enqueue_decompress(ctx, l, static_cast<const uint8_t*>(d_in), n, dt, payload, d_out, s, true)) !=
-      FALCON_OK)
-    return st;
-  if ((st = dev_err(hipStreamSynchronize(s))) != FALCON_OK) return st;
-  return decompress_failed(l) ? FALCON_ERR_CORRUPT_STREAM : FALCON_OK;
+  if (out_cap_bytes / es < n) return end_call(ctx, s, FALCON_ERR_BUFFER_TOO_SMALL);
+  if (n && (!d_out || ((uintptr_t)d_out % es))) return end_call(ctx, s, FALCON_ERR_INVALID_ARG);
+  if (n)
+    st = enqueue_decompress(ctx, l, static_cast<const uint8_t*>(d_in), in_len, n, dt, payload, d_out, s, true, false);
+  return end_call(ctx, s, st);
+}
+
+// The one-series-per-launch path over many series: one asynchronous call per
+// series, lengths written by the kernels to a device array, one wait.
+falcon_status falcon_compress_each(falcon_ctx* ctx, falcon_series* ss, size_t count, void* stream) {
+  if (!ctx || (count && !ss)) return FALCON_ERR_INVALID_ARG;
+  for (size_t i = 0; i < count; ++i) {
+    const falcon_status st = batch_check(FALCON_OP_COMPRESS, ss[i]);
+    if (st != FALCON_OK) return st;
+  }
+  if (count == 0) return FALCON_OK;
+  hipStream_t s = call_stream(ctx, stream);
+  falcon_status st = begin_call(ctx, s);
+  if (st != FALCON_OK) return st;
+  std::vector<uint64_t*> dl(count);
+  for (size_t i = 0; i < count && st == FALCON_OK; ++i) {
+    st = pending_length(ctx, &ss[i].out_len, &dl[i]);
+    if (st == FALCON_OK)
+      st = enqueue_compress(ctx, ctx->main, ss[i].d_in, ss[i].n, ss[i].dtype, ss[i].d_out, s, false, 0,
+                            ctx->compress_form, dl[i]);
+    if (st == FALCON_OK && ss[i].n == 0) st = empty_length(dl[i], s);
+  }
+  st = end_call(ctx, s, st);
+  const falcon_status sy = falcon_sync(ctx);
+  return st != FALCON_OK ? st : sy;
+}
+
+falcon_status falcon_decompress_each(falcon_ctx* ctx, falcon_series* ss, size_t count, void* stream) {
+  if (!ctx || (count && !ss)) return FALCON_ERR_INVALID_ARG;
+  for (size_t i = 0; i < count; ++i) {
+    const falcon_status st = batch_check(FALCON_OP_DECOMPRESS, ss[i]);
+    if (st != FALCON_OK) return st;
+  }
+  if (count == 0) return FALCON_OK;
+  hipStream_t s = call_stream(ctx, stream);
+  falcon_status st = begin_call(ctx, s);
+  if (st != FALCON_OK) return st;
+  for (size_t i = 0; i < count && st == FALCON_OK; ++i) {
+    if (ss[i].n)
+      st = enqueue_decompress(ctx, ctx->main, static_cast<const uint8_t*>(ss[i].d_in), ss[i].in_len, ss[i].n,
+                              ss[i].dtype, kPayloadFromHeader, ss[i].d_out, s, false, false);
+    ss[i].out_len = ss[i].n;
+  }
+  st = end_call(ctx, s, st);
+  const falcon_status sy = falcon_sync(ctx);
+  return st != FALCON_OK ? st : sy;
 }
 
 falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms) {
   if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
   if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
-  return dev_err(hipEventElapsedTime(ms, ctx->ev[ctx->timed_compress ? 0 : 2], ctx->ev[3]));
+  return dev_err(hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[3]));
 }
 
 falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms) {

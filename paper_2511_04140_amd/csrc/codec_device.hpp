@@ -262,6 +262,22 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
   return rl(v, 0) + rl(v, 16) + rl(v, 32) + rl(v, 48);
 }
 
+// Wave-wide sum of 64-bit values (uniform result), modulo 2^64.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+  auto step = [&](auto ctrl_tag) {
+    constexpr int C = decltype(ctrl_tag)::value;
+    v += ((uint64_t)dpp<C>((uint32_t)(v >> 32)) << 32) | dpp<C>((uint32_t)v);
+  };
+  step(std::integral_constant<int, kDppXor1>{});
+  step(std::integral_constant<int, kDppXor2>{});
+  step(std::integral_constant<int, kDppHalfMirror>{});
+  step(std::integral_constant<int, kDppMirror>{});
+  uint64_t m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) m += ((uint64_t)rl((uint32_t)(v >> 32), 16 * r) << 32) | rl((uint32_t)v, 16 * r);
+  return m;
+}
+
 // Lane L receives v from lane L ^ B: quad permutes for 1 and 2, a row
 // rotate by 8 for 8, a swizzle inside 32-lane halves for 4 and 16, a
 // backward permute for 32.

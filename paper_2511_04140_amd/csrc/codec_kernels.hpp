@@ -412,14 +412,14 @@ struct ChunkPlanes {
   uint32_t w;
 };
 
-// a4-a7 once the chunk's case is known (cp.A, cp.B set): Eq. 3, Eq. 4, bit
-// width, and the transpose (TRANSPOSE) or, for the size pass, only the ORs
-// of each byte's eight elements (which decide whether a row byte is zero).
-// vb is consumed (free for the next chunk's loads when this returns).
-template <class T, bool TRANSPOSE = true>
-__device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t* buf,
-                                                   const typename T::U (&vb)[17], int lane_in, bool case1,
-                                                   ChunkPlanes& cp) {
+// a4-a6 once the chunk's case is known (cp.A, cp.B set): Eq. 3, Eq. 4 and
+// the bit width.  e receives this lane's entries of the delta sequence in
+// the contiguous layout; with ORS, cp.or0 / cp.or1 receive the ORs of each
+// row byte's eight elements (which decide whether a row byte is zero).  vb
+// is consumed (free for the next chunk's loads when this returns).
+template <class T, bool ORS>
+__device__ __forceinline__ void transform_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
+                                                int lane_in, bool case1, ChunkPlanes& cp, typename T::U (&e)[16]) {
   using U = typename T::U;
   using F = typename T::F;
   // An opaque copy of the lane index keeps the compiler from hoisting the
@@ -453,7 +453,6 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
   wave_lds_sync();
 
   // a5: Eq. 4 in the contiguous layout: e[q] = z_{16L+q+2}
-  U e[16];
   {
     const uint32_t b0 = 17u * lane;
     U prev = g[b0];
@@ -478,8 +477,7 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
     const uint32_t o = wave_or32((uint32_t)orv);
     cp.w = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
   }
-
-  if constexpr (!TRANSPOSE) {
+  if constexpr (ORS) {
     U o0 = 0, o1 = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -488,10 +486,15 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
     }
     cp.or0 = (uint64_t)o0;
     cp.or1 = (uint64_t)o1;
-    return;
   }
-  // a7: bit-plane transpose; element q of the lane goes to row q ^ 7 so that
-  // the first element of each byte lands in its most significant bit.
+}
+
+// a7: bit-plane transpose of the entries e (contiguous layout) into cp.lo /
+// cp.hi; element q of the lane goes to row q ^ 7 so that the first element
+// of each byte lands in its most significant bit.
+template <class T>
+__device__ __forceinline__ void transform_planes(ChunkPlanes& cp, const typename T::U (&e)[16]) {
+  using U = typename T::U;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     cp.lo[i] = (uint32_t)e[i ^ 7];
@@ -501,6 +504,17 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
   // with w <= 32 every upper half is zero, and so is its transpose
   if constexpr (sizeof(U) == 8)
     if (cp.w > 32) xpose16(cp.hi);
+}
+
+// a4-a7: the transform, then the transpose (TRANSPOSE) or, for the size
+// pass, only the row-byte ORs.
+template <class T, bool TRANSPOSE = true>
+__device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t* buf,
+                                                   const typename T::U (&vb)[17], int lane, bool case1,
+                                                   ChunkPlanes& cp) {
+  typename T::U e[16];
+  transform_front<T, !TRANSPOSE>(sm, buf, vb, lane, case1, cp, e);
+  if constexpr (TRANSPOSE) transform_planes<T>(cp, e);
 }
 
 // a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
@@ -935,10 +949,10 @@ __device__ __forceinline__ Series find_series(const Series& one, const Series* m
 
 // Writes the 32-byte header of every empty series of a batch launch and its
 // stream length (no chunk of the launch belongs to them).  Run by the first
-// workgroup of a batch launch (one with a length array), one thread per
-// series.
+// workgroup of a batch launch (one with a descriptor array and a length
+// array), one thread per series.
 __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
-  if (!a.lens || blockIdx.x != 0) return;
+  if (!a.lens || !a.many || blockIdx.x != 0) return;
   for (uint32_t i = threadIdx.x; i < a.nseries; i += blockDim.x) {
     const CompressSeries& sd = a.many[i];
     if (sd.n != 0) continue;
@@ -1086,6 +1100,275 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   }
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass compression (Sec. 3.4): one launch computes every chunk and
+// writes it at its offset.  Waves take chunks from a work queue (atomic
+// ticket counters, see take_ticket), so chunks start close to launch order,
+// and each chunk finds its offset with a decoupled look-back over per-chunk
+// status words:
+//   1. a1-a6 and the row statistics give the chunk's size S, published at
+//      once as an aggregate (A, S); a series' first chunk publishes its
+//      inclusive prefix (P, S) instead;
+//   2. the transpose and the payload assembly (at byte phase 0 in LDS) run
+//      while the chunks before it publish their sizes;
+//   3. the look-back reads the 64 status words before the chunk, adds the
+//      aggregates up to the nearest inclusive prefix and publishes (P, O + S);
+//   4. the payload goes to its offset O, shifted to the destination's byte
+//      phase on the way out of LDS.
+// A chunk waits only for smaller chunks.  The smallest unfinished chunk
+// never waits: if a wave holds it, every chunk before it is done; if not,
+// every chunk its counter has handed out is smaller and done, so the waves
+// of that counter are free to take it.  So the queue always drains, with
+// or without other kernels on the device.  The look-back's wait is nevertheless
+// bounded: past kSpinLimit rereads (or once another wave has given up) it
+// gives up, sets ctl->qerror and the chunk writes nothing; its successors
+// then compute offsets that are too small, never too large, and every
+// payload write is also checked against the nc chunk bounds the caller's
+// buffer holds, so nothing is written out of bounds.
+// ---------------------------------------------------------------------------
+// Status word: bits 63..62 kind (1 = aggregate, 2 = inclusive prefix),
+// bits 61..46 the launch's tag, bits 45..0 the byte count.
+constexpr uint64_t kStAgg = 1ull << 62, kStPre = 2ull << 62;
+constexpr uint64_t kStValMask = (1ull << 46) - 1;
+constexpr uint64_t kStTagMask = 0xFFFFull << 46;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ uint64_t status_word(uint64_t kind, uint32_t tag, uint64_t v) {
+  return kind | ((uint64_t)(tag & 0xFFFFu) << 46) | (v & kStValMask);
+}
+
+// The next chunk of the calling wave (lane 0 takes the ticket; every lane
+// gets the chunk).  Counter g hands out chunks g, g + G, g + 2G, ... in
+// increasing order to the workgroups b = g mod G; one counter would
+// serialise every chunk on one memory location.
+__device__ __forceinline__ uint64_t take_ticket(const CompressArgs& a, int lane) {
+  const uint32_t g = blockIdx.x % a.qgroups;
+  uint64_t k = 0;
+  if (lane == 0)
+    k = __hip_atomic_fetch_add(a.qctr + (size_t)kQueueStride * g, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return uniform64(k) * a.qgroups + g;
+}
+
+// Exclusive prefix of the sizes of the chunks tf .. tg - 1 (tf = launch
+// index of the series' first chunk, tg > tf): the aggregates of the chunks
+// before tg back to the nearest inclusive prefix, plus that prefix.  Lane L
+// reads the status word of chunk j - 1 - L; positions before tf act as an
+// inclusive prefix of 0.  Sets failed (uniform) after kSpinLimit rereads of
+// a window with a word still unpublished.
+__device__ __forceinline__ uint64_t look_back(const CompressArgs& a, uint64_t tg, uint64_t tf, int lane,
+                                              bool& failed) {
+  const uint64_t tag = (uint64_t)(a.qtag & 0xFFFFu) << 46;
+  uint64_t acc = 0;
+  uint64_t j = tg;
+  uint32_t spins = 0;
+  for (;;) {
+    const bool edge = j < tf + 1 + (uint64_t)lane;  // j - 1 - lane < tf
+    uint64_t w = 0;
+    if (!edge) w = __hip_atomic_load(a.status + (j - 1 - lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool mine = (w & kStTagMask) == tag;
+    const bool pre = edge || (mine && (w >> 62) == 2);
+    const bool ready = pre || (mine && (w >> 62) == 1);
+    const uint64_t pm = ballot(pre);
+    const uint32_t s = pm ? (uint32_t)__builtin_ctzll(pm) : 64u;
+    // lanes 0 .. s must all hold a published word
+    const uint64_t upto = s >= 63 ? ~0ull : ((2ull << s) - 1);
+    if ((ballot(!ready) & upto) == 0) {
+      acc += wave_sum64(((uint32_t)lane <= s && !edge) ? (w & kStValMask) : 0ull);
+      if (s < 64) return acc;
+      j -= 64;
+      continue;
+    }
+    // give up past the limit, or at once when another wave has given up
+    // (every 256 rereads the shared error word is checked)
+    ++spins;
+    if (spins > kSpinLimit ||
+        ((spins & 255u) == 0 &&
+         __hip_atomic_load(&a.ctl->qerror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+      failed = true;
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// a11 for the single pass: copies a payload assembled at phase 0 (buf holds
+// its S bytes) to dst, which may have any byte phase ph = dst & 15.  Whole
+// 16-byte destination blocks are built from five aligned LDS dwords shifted
+// by the phase (v_alignbyte) and stored with one 16-byte store each; the
+// partial first and last blocks are written byte by byte, one byte per lane
+// (lanes 0-15 the first block, 16-31 the last).
+__device__ __forceinline__ void copy_payload_shifted(const uint8_t* buf, uint8_t* dst, uint32_t S, int lane) {
+  const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
+  uint8_t* const dal = dst - ph;
+  const uint32_t end = ph + S;
+  const uint32_t nblk = (end + 15) >> 4;
+  const uint32_t r = (16u - ph) & 3u;  // byte shift inside a dword (uniform)
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(buf);
+  // whole blocks: 16k >= ph and 16k + 16 <= end
+  const uint32_t k0 = ph ? 1u : 0u;
+  const uint32_t k1 = end >> 4;  // blocks below k1 end at or before `end`
+  for (uint32_t k = k0 + (uint32_t)lane; k < k1; k += 64) {
+    const uint32_t x = 16u * k - ph;  // first payload byte of the block
+    const uint32_t d0 = x >> 2;
+    const uint32_t w0 = bw[d0], w1 = bw[d0 + 1], w2 = bw[d0 + 2], w3 = bw[d0 + 3], w4 = bw[d0 + 4];
+    uint4 v;
+    v.x = __builtin_amdgcn_alignbyte(w1, w0, r);
+    v.y = __builtin_amdgcn_alignbyte(w2, w1, r);
+    v.z = __builtin_amdgcn_alignbyte(w3, w2, r);
+    v.w = __builtin_amdgcn_alignbyte(w4, w3, r);
+    gstore16(dal + 16u * k, v);
+  }
+  // partial blocks: the first if ph > 0 (or the payload ends inside it), the
+  // last if end is not block aligned and it is not the first
+  const uint32_t j = (uint32_t)lane & 15u;
+  if (lane < 16) {
+    const bool partial = ph != 0 || end < 16;
+    if (partial && j >= ph && j < end) gbl(dal)[j] = buf[j - ph];
+  } else if (lane < 32) {
+    const uint32_t kl = nblk - 1;
+    const uint32_t p = 16u * kl + j;
+    if (kl > 0 && (end & 15u) != 0 && p < end) gbl(dal)[p] = buf[p - ph];
+  }
+}
+
+// One chunk of the single pass, executed by one wave.  vb holds its values;
+// next() runs once the chunk's offset is known: it takes the wave's next
+// ticket and loads that chunk into vb (so the ticket is drawn when the wave
+// is about to start it, and chunks publish their sizes close to ticket
+// order), and the loads overlap this chunk's payload copy.
+template <class T, class Next>
+__device__ __forceinline__ void queue_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
+                                            const CompressSeries& sd, uint64_t tg, int lane,
+                                            typename T::U (&vb)[17], Next&& next) {
+  const uint64_t c = tg - sd.chunk0;
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  // a2-a6 and the row statistics (a8-a9)
+  ChunkPlanes cp;
+  bool case1;
+  decide_case<T>(tab, vb, cp.A, cp.B, case1);
+  typename T::U e[16];
+  transform_front<T, true>(tab, buf, vb, lane, case1, cp, e);
+  const ChunkStats st = chunk_stats_or<T>(cp, lane);
+  const uint32_t S = uniform(st.S);
+  const uint64_t flags = uniform64(st.flags);
+  // step 1: publish the size
+  if (lane == 0) {
+    __hip_atomic_store(a.status + tg, status_word(c == 0 ? kStPre : kStAgg, a.qtag, S), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    gbl(reinterpret_cast<uint32_t*>(sd.out + kHdrBytes))[c] = S;
+  }
+  // step 2: a7 and the payload at phase 0
+  transform_planes<T>(cp, e);
+  assemble_payload<T>(buf, cp, flags, S, lane);
+  // step 3: the offset
+  bool failed = false;
+  const uint64_t off = c == 0 ? 0 : look_back(a, tg, sd.chunk0, lane, failed);
+  // a payload always ends within nc chunk bounds of the payload's start
+  // (the caller's buffer holds at least that much): a look-back that gave
+  // up, or any offset past that, writes nothing
+  failed = failed || off + S > nc * (uint64_t)T::BOUND;
+  if (c != 0 && lane == 0)
+    __hip_atomic_store(a.status + tg, status_word(kStPre, a.qtag, off + S), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  next();
+  wave_lds_sync();
+  // step 4: the payload at its offset
+  if (!failed) copy_payload_shifted(buf, sd.out + kHdrBytes + 4 * nc + off, S, lane);
+  else if (lane == 0) __hip_atomic_store(&a.ctl->qerror, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (c == nc - 1) {
+    write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
+    if (a.lens && lane == 0) a.lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
+  }
+  wave_lds_sync();
+}
+
+// One dtype per launch.  Every wave takes chunks until it draws one past
+// the last.
+template <class T, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_queue(CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  pass_prologue(sm, a, true);
+  const int lane = lane_id();
+  const int wid = (int)uniform(threadIdx.x >> 6);
+  uint8_t* buf = wave_bytes(sm, wid);
+  typename T::U vb[17];
+  if (a.total_chunks == 0 && !a.many && blockIdx.x == 0 && wid == 0)
+    write_stream_header(a.one.out, a.one.dtype, 0, 0, lane);
+  uint64_t t = take_ticket(a, lane);
+  if (t >= a.total_chunks) return;
+  CompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
+  load_chunk<T>(sd, t + a.t0 - sd.chunk0, lane, vb);
+  for (;;) {
+    const CompressSeries cur = sd;
+    uint64_t tn = 0;
+    bool more = false;
+    auto next = [&]() {
+      tn = take_ticket(a, lane);
+      more = tn < a.total_chunks;
+      if (more) {
+        sd = find_series(a.one, a.many, a.nseries, tn + a.t0);
+        load_chunk<T>(sd, tn + a.t0 - sd.chunk0, lane, vb);
+      }
+    };
+    queue_chunk<T>(sm.tab, buf, a, cur, t + a.t0, lane, vb, next);
+    if (!more) break;
+    t = tn;
+  }
+}
+
+// Both dtypes in one launch: the wave branches on the dtype of each chunk's
+// series (no prefetch across chunks).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_queue_mixed(
+    CompressArgs a) {
+  __shared__ BlockLdsT<NW> sm;
+  pass_prologue(sm, a, true);
+  const int lane = lane_id();
+  const int wid = (int)uniform(threadIdx.x >> 6);
+  uint8_t* buf = wave_bytes(sm, wid);
+  auto none = []() {};
+  for (;;) {
+    const uint64_t t = take_ticket(a, lane);
+    if (t >= a.total_chunks) break;
+    const uint64_t tg = t + a.t0;
+    const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
+    if (uniform(sd.dtype) == 2) {
+      uint64_t vb[17];
+      load_chunk<TF64>(sd, tg - sd.chunk0, lane, vb);
+      queue_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, none);
+    } else {
+      uint32_t vb[17];
+      load_chunk<TF32>(sd, tg - sd.chunk0, lane, vb);
+      queue_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, none);
+    }
+  }
+}
+
+// A one-series launch whose header the host has not read
+// (payload_bytes == kFromHeader): the header is read here and checked
+// against the descriptor (magic, version, dtype, chunk length, zero fields,
+// value count, payload bytes within in_len).  A header that fails leaves a
+// payload of 0, so that every chunk then fails its bounds check, and stores
+// the launch epoch in the error word.  Wave-uniform (scalar loads).
+constexpr uint64_t kFromHeader = ~0ull;
+__device__ __forceinline__ DecompressSeries resolve_header(const DecompressArgs& a, int lane) {
+  DecompressSeries sd = a.one;
+  asm volatile("" ::: "memory");
+  if (a.many || sd.payload_bytes != kFromHeader) return sd;
+  const const_ptr<uint32_t> h = cst(reinterpret_cast<const uint32_t*>(sd.in));
+  uint32_t w[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w[i] = h[i];
+  const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
+  const uint64_t payload = (uint64_t)w[6] | ((uint64_t)w[7] << 32);
+  const bool ok = w[0] == 0x4E434C46u && w[1] == (1u | (sd.dtype << 8)) && w[2] == (uint32_t)kChunk && w[3] == 0 &&
+                  ((uint64_t)w[4] | ((uint64_t)w[5] << 32)) == sd.n && sd.in_len >= kHdrBytes + 4 * nc &&
+                  payload <= sd.in_len - kHdrBytes - 4 * nc;
+  sd.payload_bytes = ok ? payload : 0;
+  if (!ok && lane == 0) __hip_atomic_store(&a.ctl->error, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return sd;
+}
+
 // Decompression has no dependence between chunks once the offsets are
 // known, so waves take chunks by static striding and use no counter.  Each
 // wave loads the payload of its next chunk into registers while it decodes
@@ -1096,7 +1379,8 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
                                                 Dispatch&& dispatch) {
   uint64_t t = (uint64_t)blockIdx.x * kWavesD + wid;
   if (t >= a.total_chunks) return;
-  DecompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
+  const DecompressSeries one = resolve_header(a, lane);
+  DecompressSeries sd = find_series(one, a.many, a.nseries, t + a.t0);
   Staged st = stage_issue(sd, t + a.t0, a.offsets, a.relative != 0, lane, true);
   // Seventeen stores with an empty window (dropped, no memory access): the
   // loop is then entered, as it is re-entered, with the value stores of a
@@ -1118,7 +1402,7 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
     // the next chunk's loads; past the last chunk the same instructions run
     // on the current chunk with an empty window (no memory access)
     const uint64_t tq = more ? tn : t;
-    sd = find_series(a.one, a.many, a.nseries, tq + a.t0);
+    sd = find_series(one, a.many, a.nseries, tq + a.t0);
     st = stage_issue(sd, tq + a.t0, a.offsets, a.relative != 0, lane, more);
     dispatch(cur, c, S, pad, total, bad);
     if (!more) break;

@@ -40,12 +40,21 @@ struct Lane {
   uint64_t* tiles = nullptr;    // scan tile sums
   size_t tiles_cap = 0;
   falcon_dev::Ctl* ctl = nullptr;
-  uint8_t* stage = nullptr;     // pinned host bytes: [0,32) header, [32,36) error word, [40,48) payload size
+  uint8_t* stage = nullptr;     // pinned host bytes: [0,32) header, [32,40) copy of the control block's
+                                // two error words, [40,48) payload size
   uint32_t epoch = 0;
   falcon_dev::ChunkMeta* meta = nullptr;  // compression size pass results, one per chunk
   size_t meta_cap = 0;
   uint32_t* gsizes = nullptr;             // compression chunk sizes (scan input)
   size_t gsizes_cap = 0;
+  // single-pass compression: one status word per chunk (look-back), the
+  // 16-bit tag of the last launch's words (the array is cleared whenever the
+  // tag wraps or the array is reallocated), and the ticket counters
+  // (kQueueGroups x kQueueStride words, cleared before every launch)
+  uint64_t* status = nullptr;
+  size_t status_cap = 0;
+  uint32_t qtag = 0;
+  uint64_t* qctr = nullptr;
 };
 
 falcon_status lane_init(Lane& l);
@@ -110,12 +119,34 @@ struct BatchScratch {
 
 struct falcon_ctx {
   int device = 0;
+  unsigned opt_flags = 0;   // FALCON_OPT_* of falcon_create
+  int compress_form = 0;    // falcon_compress_form of falcon_compress
   falcon_host::Lane main;
+  // asynchronous device calls: every call waits (on the device) for the
+  // previous one when it uses another stream, and records ev_done after its
+  // work; falcon_sync waits for last_stream
+  hipEvent_t ev_done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool unsynced = false;
+  uint32_t sync_epoch = 0;  // main lane's launch epoch at the last falcon_sync
+  // stream lengths of compressions that report to host memory: the kernels
+  // write them into device words (blocks of kLenBlock, never moved while in
+  // use), falcon_sync copies them to pinned memory and on to the caller
+  std::vector<uint64_t*> len_blocks;
+  uint64_t* len_host = nullptr;  // pinned, len_host_cap words
+  size_t len_host_cap = 0;
+  struct PendingLen {
+    size_t* dst;
+    size_t slot;
+  };
+  std::vector<PendingLen> pending;
   // co-resident workgroups of each kernel: by form (1 = f32, 2 = f64,
   // 3 = mixed) and, for compression, pass (0 single-pass, 1 size, 2 write)
   // and workgroup size (8 or 16 waves)
   int grid_c[4][3][2] = {};
   int grid_d[4] = {};
+  // the same for the single-pass compression kernels: [form][8 or 16 waves]
+  int grid_q[4][2] = {};
   // the same for the ablation-variant compression kernels: [form][variant][pass]
   int grid_v[3][4][3] = {};
   // events of the last timed call: before the first kernel, after it, after
@@ -146,17 +177,25 @@ namespace falcon_host {
 // around the kernel feed falcon_last_kernel_ms.  variant != 0 selects an
 // ablation variant's kernels (falcon_variant).
 falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint64_t n, falcon_dtype dt, void* d_out,
-                               hipStream_t s, bool timed, int variant = 0);
+                               hipStream_t s, bool timed, int variant = 0, int form = 0, uint64_t* d_len = nullptr);
+constexpr size_t kLenBlock = 4096;  // stream-length words per device block of a context
 
-// Enqueues the decompression of a stream at d_in whose header (n, dt,
-// payload) the host already knows and has checked, into d_out, followed by
-// a copy of the error word into l.stage + 32.  decompress_failed() afterwards
-// (once the stream has reached that copy) tells whether a chunk failed.
-falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t n, falcon_dtype dt,
-                                 uint64_t payload, void* d_out, hipStream_t s, bool timed);
+// Enqueues the decompression of a stream at d_in of in_len bytes holding n
+// values of type dt, into d_out.  With payload = kPayloadFromHeader the
+// stream header is read and checked on the device (against n, dt, in_len);
+// otherwise the host has checked it and payload is its byte count.  With
+// copy_error the error word is then copied into l.stage + 32, and
+// decompress_failed() afterwards (once the stream has reached that copy)
+// tells whether a chunk failed.
+constexpr uint64_t kPayloadFromHeader = ~0ull;
+falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, uint64_t in_len, uint64_t n,
+                                 falcon_dtype dt, uint64_t payload, void* d_out, hipStream_t s, bool timed,
+                                 bool copy_error = true);
 inline bool decompress_failed(const Lane& l) { return rd32(l.stage + 32) == l.epoch; }
 
+
 inline int max_grid_c(const falcon_ctx* ctx, int form, int pass, int nw);
+inline int max_grid_q(const falcon_ctx* ctx, int form, int nw) { return ctx->grid_q[form][nw == 8 ? 0 : 1]; }
 inline int max_grid_d(const falcon_ctx* ctx, int form);
 
 // Frees the pipeline lanes and their buffers (pipeline.cpp).

@@ -7,12 +7,22 @@
 
 namespace falcon_dev {
 
-// Control block of a decompression launch: an error word that receives the
-// launch epoch when a chunk fails a check.
+// Control block of a launch queue: the decompression error word (receives
+// the launch epoch when a chunk fails a check), the single-pass compression
+// error word (set when a look-back gives up, which a correct run never
+// does) and the work-queue ticket counter of single-pass compression.
 struct Ctl {
   uint32_t error;
-  uint32_t pad[3];
+  uint32_t qerror;
+  uint64_t pad;
 };
+
+// Single-pass compression takes chunks from kQueueGroups ticket counters,
+// each in a 128-byte line of its own (a counter is one word every
+// kQueueStride): workgroup b draws from counter b mod G and its ticket k
+// stands for launch chunk k * G + (b mod G).
+constexpr int kQueueGroups = 16;
+constexpr int kQueueStride = 16;
 
 // One array to compress.  chunk0 is the global index of its first chunk in
 // the launch (prefix of the chunk counts of the series before it).
@@ -57,7 +67,15 @@ struct CompressArgs {
   uint32_t* gsizes;    // chunk sizes by launch chunk (scan input), written by the size pass
   const uint64_t* offsets;  // exclusive prefix of gsizes, read by the write pass
   uint32_t relative;   // 1: offsets run over all series; a series subtracts its first one
-  uint32_t pad;
+  uint32_t qtag;       // single pass: 16-bit tag of this launch's status words (never 0)
+  // single pass (work queue and look-back): qgroups ticket counters at
+  // qctr[kQueueStride * g], all 0 at the launch's start; status holds one
+  // word per launch chunk
+  uint64_t* status;
+  uint64_t* qctr;
+  Ctl* ctl;
+  uint32_t qgroups;
+  uint32_t pad2;
 };
 
 struct DecompressArgs {
@@ -84,6 +102,17 @@ constexpr int kFormMixed = 3;
 // arrays); pass 2: the write pass, after a scan of gsizes into offsets.
 hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs& a, int form, int grid, hipStream_t s);
+// Single-pass compression (work queue over chunks, decoupled look-back for
+// the offsets): a.status / a.qctr / a.qgroups (<= grid) / a.ctl / a.qtag
+// set, the a.qgroups counters cleared beforehand.
+hipError_t launch_compress_queue(const CompressArgs& a, int form, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_queue_f64(const CompressArgs& a, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_queue_f32(const CompressArgs& a, int nw, int grid, hipStream_t s);
+hipError_t launch_compress_queue_mixed(const CompressArgs& a, int nw, int grid, hipStream_t s);
+const void* compress_queue_kernel_f64(int nw);
+const void* compress_queue_kernel_f32(int nw);
+const void* compress_queue_kernel_mixed(int nw);
+int max_grid_compress_queue(int device, int form, int nw);
 // per-form entry points (one translation unit each)
 hipError_t launch_compress_f64(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);
 hipError_t launch_compress_f32(const CompressArgs& a, int pass, int nw, int grid, hipStream_t s);

@@ -149,6 +149,12 @@ hipError_t launch_compress(const CompressArgs& a, int form, int pass, int nw, in
   return launch_compress_mixed(a, pass, nw, grid, s);
 }
 
+hipError_t launch_compress_queue(const CompressArgs& a, int form, int nw, int grid, hipStream_t s) {
+  if (form == 2) return launch_compress_queue_f64(a, nw, grid, s);
+  if (form == 1) return launch_compress_queue_f32(a, nw, grid, s);
+  return launch_compress_queue_mixed(a, nw, grid, s);
+}
+
 hipError_t launch_compress_variant(const CompressArgs& a, int form, int variant, int pass, int grid, hipStream_t s) {
   const void* fn = form == 2 ? compress_variant_kernel_f64(variant, pass)
                              : form == 1 ? compress_variant_kernel_f32(variant, pass) : nullptr;
@@ -195,6 +201,12 @@ static int max_grid_of(const void* fn, int device, int block) {
 int max_grid_compress(int device, int form, int pass, int nw) {
   const void* fn = form == 2 ? compress_kernel_f64(pass, nw)
                              : form == 1 ? compress_kernel_f32(pass, nw) : compress_kernel_mixed(pass, nw);
+  return max_grid_of(fn, device, 64 * nw);
+}
+
+int max_grid_compress_queue(int device, int form, int nw) {
+  const void* fn = form == 2 ? compress_queue_kernel_f64(nw)
+                             : form == 1 ? compress_queue_kernel_f32(nw) : compress_queue_kernel_mixed(nw);
   return max_grid_of(fn, device, 64 * nw);
 }
 

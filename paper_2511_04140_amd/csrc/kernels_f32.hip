@@ -46,4 +46,15 @@ const void* compress_variant_kernel_f32(int variant, int pass) {
 
 const void* decompress_kernel_f32() { return reinterpret_cast<const void*>(&k_decompress<TF32>); }
 
+hipError_t launch_compress_queue_f32(const CompressArgs& a, int nw, int grid, hipStream_t s) {
+  if (nw == 8) hipLaunchKernelGGL((k_compress_queue<TF32, 8>), dim3(grid), dim3(64 * 8), 0, s, a);
+  else hipLaunchKernelGGL((k_compress_queue<TF32, 16>), dim3(grid), dim3(64 * 16), 0, s, a);
+  return hipGetLastError();
+}
+
+const void* compress_queue_kernel_f32(int nw) {
+  return nw == 8 ? reinterpret_cast<const void*>(&k_compress_queue<TF32, 8>)
+                 : reinterpret_cast<const void*>(&k_compress_queue<TF32, 16>);
+}
+
 }  // namespace falcon_dev

@@ -48,4 +48,15 @@ const void* compress_kernel_mixed(int pass, int nw) { return nw == 8 ? kernel_nw
 
 const void* decompress_kernel_mixed() { return reinterpret_cast<const void*>(&k_decompress_mixed); }
 
+hipError_t launch_compress_queue_mixed(const CompressArgs& a, int nw, int grid, hipStream_t s) {
+  if (nw == 8) hipLaunchKernelGGL((k_compress_queue_mixed<8>), dim3(grid), dim3(64 * 8), 0, s, a);
+  else hipLaunchKernelGGL((k_compress_queue_mixed<16>), dim3(grid), dim3(64 * 16), 0, s, a);
+  return hipGetLastError();
+}
+
+const void* compress_queue_kernel_mixed(int nw) {
+  return nw == 8 ? reinterpret_cast<const void*>(&k_compress_queue_mixed<8>)
+                 : reinterpret_cast<const void*>(&k_compress_queue_mixed<16>);
+}
+
 }  // namespace falcon_dev

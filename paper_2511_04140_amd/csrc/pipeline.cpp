@@ -463,7 +463,7 @@ falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t i
           memcpy(p.p_in + 32 + 4 * p.nchunks, payload_base + boff[b], pb);
           if ((st = dev_err(hipMemcpyAsync(p.g_in, p.p_in, slen, hipMemcpyHostToDevice, s))) != FALCON_OK) goto fail;
         }
-        if ((st = enqueue_decompress(ctx, p.lane, p.g_in, p.nvals, dt, pb, p.g_out, s, false)) != FALCON_OK ||
+        if ((st = enqueue_decompress(ctx, p.lane, p.g_in, slen, p.nvals, dt, pb, p.g_out, s, false)) != FALCON_OK ||
             (st = dev_err(hipMemcpyAsync(out_pinned ? out + v0 * es : p.p_out, p.g_out, p.nvals * es,
                                          hipMemcpyDeviceToHost, s))) != FALCON_OK ||
             (st = dev_err(hipEventRecord(p.ev, s))) != FALCON_OK)

@@ -20,7 +20,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("falcon_create", "falcon_destroy", "falcon_compress_bound", "falcon_compress",
-                 "falcon_decompress", "falcon_stream_info", "falcon_status_str"):
+                 "falcon_decompress", "falcon_decompress_n", "falcon_sync", "falcon_stream_info",
+                 "falcon_status_str", "falcon_compress_each", "falcon_decompress_each"):
         assert want in names
 
 
@@ -78,7 +79,7 @@ def test_struct_layouts_match_the_binding(tmp_path):
     import sys
     sys.path.insert(0, ROOT)
     from paper_2511_04140_amd import codec as C
-    pairs = [(C.Series, "falcon_series"), (C.PlanInfo, "falcon_plan_info"),
+    pairs = [(C.Opts, "falcon_opts"), (C.Series, "falcon_series"), (C.PlanInfo, "falcon_plan_info"),
              (C.ServerOpts, "falcon_server_opts"), (C.Request, "falcon_request"),
              (C.Completion, "falcon_completion")]
     body = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', 'int main(void) {']
@@ -96,3 +97,16 @@ def test_struct_layouts_match_the_binding(tmp_path):
     subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert [int(v) for v in out] == want
+
+
+def test_create_rejects_unknown_options():
+    """falcon_create checks its options on the host before touching a device:
+    unknown flag bits or form give FALCON_ERR_INVALID_ARG (no GPU needed)."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2511_04140_amd import codec as C
+    L = C.lib()
+    ctx = ctypes.c_void_p()
+    for opts in (C.Opts(0x80, 0), C.Opts(0, 7), C.Opts(0, -1)):
+        assert L.falcon_create(0, ctypes.byref(opts), ctypes.byref(ctx)) == 1
+    assert L.falcon_create(0, None, None) == 1
