@@ -140,6 +140,29 @@ size_t falcon_compress_bound(size_t n, falcon_dtype dt);
 falcon_status falcon_compress(falcon_ctx* ctx, const void* d_in, size_t n, falcon_dtype dt,
                               void* d_out, size_t out_cap, size_t* out_len, void* stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): falcon_compress
+ * (two passes, FALCON_OPT_DEVICE_LENGTHS semantics) without a context and
+ * without any allocation.  Its scratch is a fixed array of about 14 MiB in
+ * the library's device code; every GPU the library runs on holds its own
+ * copy until the process ends.  The device is the current HIP device, and
+ * `stream` (NULL: its null stream) must belong to it.  The first call on a
+ * device (or falcon_create for it) takes the array's device address; that
+ * call makes no allocation either.  Asynchronous: d_out receives the stream,
+ * and d_out_len, if not NULL, a device size_t (8-byte aligned), receives its
+ * length in stream order (the header at d_out + 24 also holds the payload
+ * byte count).  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (on different streams, or from different threads)
+ * race, so the caller orders them, for instance on one stream.  Nothing of
+ * the array needs to start at zero.  Errors: FALCON_ERR_OUT_OF_MEMORY
+ * without any launch if n exceeds 537,395,200 values (2^19 chunks of 1025),
+ * the array's limit; FALCON_ERR_BUFFER_TOO_SMALL if out_cap <
+ * falcon_compress_bound(n, dt); FALCON_ERR_INVALID_ARG for a null or
+ * misaligned pointer or an unknown dtype; FALCON_ERR_DEVICE if a HIP call
+ * fails. */
+falcon_status falcon_compress_noalloc(const void* d_in, size_t n, falcon_dtype dt, void* d_out, size_t out_cap,
+                                      size_t* d_out_len, void* stream);
+
 /* Ablation variants of Sec. 5.4.2 (Fig. 12b).  Each changes one step of
  * compression and keeps the stream layout:
  *  ELF    Alg. 2 stops at the first alpha where v (x) 10^alpha is an exact

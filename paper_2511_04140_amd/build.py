@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfalcon.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
-    "kernels_f64.hip", "kernels_f32.hip", "kernels_mixed.hip", "kernels_common.hip",
+    "kernels_f64.hip", "kernels_f32.hip", "kernels_mixed.hip", "kernels_common.hip", "noalloc.hip",
     "api.cpp", "pipeline.cpp", "batch.cpp", "serve.cpp")]
 ARCH = os.environ.get("FALCON_OFFLOAD_ARCH", "gfx950")
 

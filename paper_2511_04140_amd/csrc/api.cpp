@@ -336,6 +336,10 @@ falcon_status falcon_create(int device, const falcon_opts* opts, falcon_ctx** ou
   for (int f = 1; f <= 2; ++f)
     for (int v = 1; v <= 3; ++v)
       for (int pass = 1; pass <= 2; ++pass) ctx->grid_v[f][v][pass] = max_grid_compress_variant(device, f, v, pass);
+  if (noalloc_setup(device) != FALCON_OK) {
+    falcon_destroy(ctx);
+    return FALCON_ERR_DEVICE;
+  }
   *out = ctx;
   return FALCON_OK;
 }

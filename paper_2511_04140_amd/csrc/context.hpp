@@ -198,6 +198,10 @@ inline int max_grid_c(const falcon_ctx* ctx, int form, int pass, int nw);
 inline int max_grid_q(const falcon_ctx* ctx, int form, int nw) { return ctx->grid_q[form][nw == 8 ? 0 : 1]; }
 inline int max_grid_d(const falcon_ctx* ctx, int form);
 
+// Set-up of falcon_compress_noalloc on `device` (noalloc.hip): the device
+// address of its fixed scratch and its launch grids.
+falcon_status noalloc_setup(int device);
+
 // Frees the pipeline lanes and their buffers (pipeline.cpp).
 void pipe_release(falcon_ctx* ctx);
 
