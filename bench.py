@@ -58,37 +58,79 @@ def measured_traffic(kernel, per_launch_algo_bytes):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(x, budget_s=12.0):
-    """The oracle as it stands, single-threaded, on the leading chunks of the
-    same workload until about budget_s seconds of work have been done."""
+def _cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def _oracle_rate(x, threads, budget_s, step=1024 * 1025):
+    """Compression then decompression of chunk-aligned slices of x's leading
+    values through the oracle on `threads` threads (each slice a stream of
+    its own; the oracle's C calls release the GIL), in rounds of `threads`
+    slices until about budget_s seconds have passed.  Every round trip is
+    checked.  Returns (values done, compress seconds, decompress seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle
     import numpy as np
-    step = 2048 * 1025
     done = 0
     tc = td = 0.0
     t_start = time.perf_counter()
-    while done < x.size and time.perf_counter() - t_start < budget_s:
-        part = np.ascontiguousarray(x[done:done + step])
-        t0 = time.perf_counter()
-        s = oracle.compress(part)
-        t1 = time.perf_counter()
-        y = oracle.decompress(s)
-        t2 = time.perf_counter()
-        assert np.array_equal(y.view(np.uint8), part.view(np.uint8))
-        tc += t1 - t0
-        td += t2 - t1
-        done += part.size
+    with ThreadPoolExecutor(threads) as ex:
+        while done < x.size and time.perf_counter() - t_start < budget_s:
+            parts = [x[done + k * step: done + (k + 1) * step] for k in range(threads)]
+            parts = [p for p in parts if p.size]
+            t0 = time.perf_counter()
+            ss = list(ex.map(oracle.compress, parts))
+            t1 = time.perf_counter()
+            ys = list(ex.map(oracle.decompress, ss))
+            t2 = time.perf_counter()
+            for p_, y in zip(parts, ys):
+                assert np.array_equal(y.view(np.uint8), p_.view(np.uint8))
+            tc += t1 - t0
+            td += t2 - t1
+            done += sum(p_.size for p_ in parts)
+    return done, tc, td
+
+
+def cpu_baseline(x, x32=None, budget_s=8.0):
+    """The oracle as it stands on the host's cores (at most 16 threads, the
+    host share of one GPU), on the leading values of the benchmark workload
+    (a bounded sample, about budget_s seconds), compress + decompress; the
+    same on one thread, and on the float32 workload when given."""
+    model, nproc = _cpu_info()
+    threads = max(1, min(16, nproc))
+    done, tc, td = _oracle_rate(x, threads, budget_s)
     nbytes = done * x.itemsize
-    return {
+    out = {
         "value": round(nbytes / (tc + td) / 1e9, 6),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {done:,} values ({nbytes / 2**20:.0f} MiB) of the workload, "
-                  f"compress + decompress, single thread",
+        "sample": f"first {done:,} values ({nbytes / 2**20:.0f} MiB) of the workload in slices of "
+                  f"1,048,576+ values, compress + decompress, {threads} threads",
         "compress_gbps": round(nbytes / tc / 1e9, 6),
         "decompress_gbps": round(nbytes / td / 1e9, 6),
+        "cpu_model": model,
+        "nproc": nproc,
     }
+    d1, c1, e1 = _oracle_rate(x, 1, budget_s / 4)
+    out["one_thread"] = {"values": d1, "gbps": round(d1 * x.itemsize / (c1 + e1) / 1e9, 6),
+                         "compress_gbps": round(d1 * x.itemsize / c1 / 1e9, 6),
+                         "decompress_gbps": round(d1 * x.itemsize / e1 / 1e9, 6)}
+    if x32 is not None:
+        d2, c2, e2 = _oracle_rate(x32, threads, budget_s / 2)
+        out["float32"] = {"values": d2, "threads": threads, "gbps": round(d2 * 4 / (c2 + e2) / 1e9, 6),
+                          "compress_gbps": round(d2 * 4 / c2 / 1e9, 6),
+                          "decompress_gbps": round(d2 * 4 / e2 / 1e9, 6)}
+    return out
 
 
 def oracle_small_case(threads=None):
@@ -159,11 +201,11 @@ def host_pipeline(codec, x, torch, reps=2):
 
 def batched(codec, torch, reps=5):
     """10,000 series of uneven lengths and mixed dtypes (about 4 GB),
-    device-resident: the one-series-per-launch loop (falcon_compress /
-    falcon_decompress per series) against one tuned, graph-captured batch
-    plan over all of them; both write to buffers of their own and must give
-    identical bytes."""
-    import ctypes
+    device-resident: the one-series-per-launch path (falcon_compress_each /
+    falcon_decompress_each: a C loop of asynchronous calls, one launch
+    sequence per series, one wait at the end) against one tuned,
+    graph-captured batch plan over all of them; both write to buffers of
+    their own and must give identical bytes."""
     import numpy as np
     from paper_2511_04140_amd import codec as C
     from paper_2511_04140_amd import workloads as W
@@ -189,76 +231,58 @@ def batched(codec, torch, reps=5):
     outs = {k: torch.zeros(to, dtype=torch.uint8, device=dev) for k in ("loop", "plan")}
     ov = {k: [outs[k][o:o + b] for o, b in zip(out_off, bounds)] for k in outs}
     raw = sum(x.nbytes for x in xs)
-    L = C.lib()
-    olen = ctypes.c_size_t()
-    sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-    cargs = [(ctypes.c_void_p(v.data_ptr()), v.numel(), C._dtype_code(v.dtype), ctypes.c_void_p(o.data_ptr()),
-              o.numel()) for v, o in zip(xv, ov["loop"])]
 
-    def loop_compress():
-        lens = []
-        for a in cargs:
-            st = L.falcon_compress(codec._ctx, a[0], a[1], a[2], a[3], a[4], ctypes.byref(olen), sh)
-            assert st == 0
-            lens.append(olen.value)
-        return lens
+    def wall(fn, r):
+        best = float("inf")
+        for _ in range(r):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
 
     torch.cuda.synchronize()
-    loop_compress()
-    t0 = time.perf_counter()
-    lens = loop_compress()
-    t_loop = time.perf_counter() - t0
+    streams_loop = codec.compress_each(xv, outs=ov["loop"])
+    t_loop = wall(lambda: codec.compress_each(xv, outs=ov["loop"]), 2)
+    lens = [s_.numel() for s_ in streams_loop]
     plan = codec.plan_compress(xv, outs=ov["plan"], tune=True, graph=True)
     info = plan.info()
     plan.run(fetch=False)
-    tp = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        plan.run(fetch=False)
-        tp.append(time.perf_counter() - t0)
+    t_plan = wall(lambda: plan.run(fetch=False), reps)
     streams = plan.run()
-    identical = [s.numel() for s in streams] == lens and torch.equal(outs["loop"], outs["plan"])
+    identical = [s_.numel() for s_ in streams] == lens and torch.equal(outs["loop"], outs["plan"])
     clen = sum(lens)
     # decompression of the same streams
     dv = {k: torch.zeros(ti, dtype=torch.uint8, device=dev) for k in ("loop", "plan")}
     dviews = {k: [dv[k][o:o + x.nbytes].view(tdt(x)) for x, o in zip(xs, in_off)] for k in dv}
-    nout = ctypes.c_size_t()
-    dargs = [(ctypes.c_void_p(s.data_ptr()), s.numel(), ctypes.c_void_p(y.data_ptr()), y.numel() * y.element_size())
-             for s, y in zip(streams, dviews["loop"])]
-
-    def loop_decompress():
-        for a in dargs:
-            st = L.falcon_decompress(codec._ctx, a[0], a[1], a[2], a[3], ctypes.byref(nout), sh)
-            assert st == 0
-
-    loop_decompress()
-    t0 = time.perf_counter()
-    loop_decompress()
-    t_dloop = time.perf_counter() - t0
-    dplan = codec.plan_decompress(streams, [x.size for x in xs], [tdt(x) for x in xs], outs=dviews["plan"],
-                                  tune=True, graph=True)
+    counts, dts = [x.size for x in xs], [tdt(x) for x in xs]
+    codec.decompress_each(streams, counts, dts, outs=dviews["loop"])
+    t_dloop = wall(lambda: codec.decompress_each(streams, counts, dts, outs=dviews["loop"]), 2)
+    dplan = codec.plan_decompress(streams, counts, dts, outs=dviews["plan"], tune=True, graph=True)
     dinfo = dplan.info()
     dplan.run(fetch=False)
-    td = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        dplan.run(fetch=False)
-        td.append(time.perf_counter() - t0)
+    t_dplan = wall(lambda: dplan.run(fetch=False), reps)
     identical = identical and torch.equal(dv["loop"], dv["plan"]) and torch.equal(dv["plan"], xin)
     sizes = sorted(x.size for x in xs)
+    algo = raw + clen
+    frac = lambda t: round(algo / t / 1e9 / HBM_PEAK_GBPS, 4)
     res = {
         "series": len(xs), "f64_series": int(sum(x.dtype == np.float64 for x in xs)),
         "values_min_median_max": [sizes[0], sizes[len(sizes) // 2], sizes[-1]],
-        "bytes": raw, "ratio": round(clen / raw, 6),
-        "timing": "wall clock around each call; the per-series loop calls the C ABI once per series "
-                  "through ctypes, the batch plan replays one HIP graph",
+        "bytes": raw, "stream_bytes": clen, "ratio": round(clen / raw, 6),
+        "timing": "wall clock around each whole call, device synchronised before and after, best of runs; the "
+                  "per-series path is falcon_compress_each / falcon_decompress_each (a C loop of asynchronous "
+                  "calls, one wait), the batch path replays one tuned HIP graph",
         "compress": {"per_series_gbps": round(raw / t_loop / 1e9, 3),
-                     "batched_gbps": round(raw / min(tp) / 1e9, 3),
-                     "speedup": round(t_loop / min(tp), 2),
+                     "batched_gbps": round(raw / t_plan / 1e9, 3),
+                     "speedup": round(t_loop / t_plan, 2),
+                     "batched_hbm_frac": frac(t_plan), "per_series_hbm_frac": frac(t_loop),
                      "plan": {k: info[k] for k in ("split", "waves_per_group", "grid_percent", "candidates")}},
         "decompress": {"per_series_gbps": round(raw / t_dloop / 1e9, 3),
-                       "batched_gbps": round(raw / min(td) / 1e9, 3),
-                       "speedup": round(t_dloop / min(td), 2),
+                       "batched_gbps": round(raw / t_dplan / 1e9, 3),
+                       "speedup": round(t_dloop / t_dplan, 2),
+                       "batched_hbm_frac": frac(t_dplan), "per_series_hbm_frac": frac(t_dloop),
                        "plan": {k: dinfo[k] for k in ("split", "grid_percent", "candidates")}},
         "identical": bool(identical),
     }
@@ -267,11 +291,16 @@ def batched(codec, torch, reps=5):
     return res
 
 
-def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
+def serving(codec, torch, n_req=20000, rhos=(0.5, 0.8, 0.95), budget=64 << 30):
     """Poisson arrivals, 70% compress / 30% decompress, payloads 4 KB-64 MB
-    log-uniform, float32/float64: the served loop (continuous batching over
-    4 streams) against the plain FIFO (one request per launch), both at the
-    same offered load, rho times the FIFO's measured saturation rate."""
+    log-uniform, float32/float64.  Two paths, each with the same HBM budget:
+    the plain FIFO (one request per launch, one stream) and the served loop
+    (continuous batching over 4 streams).  Each is first driven at
+    saturation (every request submitted at once), then at offered loads of
+    rho times its own saturation rate; both are also driven at two loads
+    between the FIFO's saturation and the served loop's (geometrically
+    spaced), where the FIFO is overloaded.  Latency = completion - submission
+    of each request."""
     import numpy as np
     from paper_2511_04140_amd import codec as C
     from paper_2511_04140_amd import workloads as W
@@ -284,11 +313,12 @@ def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
     idx = rng.integers(0, len(ps), n_req)
     nbytes = np.array([p.nbytes for p in ps])
     total_bytes = int(nbytes[idx].sum())
+    gaps = rng.exponential(1.0, n_req)  # unit-rate Poisson gaps, scaled per load
 
-    def run(srv, arrivals):
+    def run(srv, lam):
+        arrivals = None if lam is None else np.cumsum(gaps / lam)
         got = []
         t_start = time.perf_counter()
-        base_us = None
         for i in range(n_req):
             if arrivals is not None:
                 t_next = t_start + arrivals[i]
@@ -301,6 +331,7 @@ def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
                 srv.submit_compress(pd[k], tag=i)
             else:
                 srv.submit_decompress(streams[k], pd[k].numel(), pd[k].dtype, tag=i)
+        t_sub = time.perf_counter() - t_start
         while len(got) < n_req:
             for c in srv.poll(20):
                 srv.release(c)
@@ -308,22 +339,38 @@ def serving(codec, torch, n_req=20000, rho=0.8, budget=64 << 30):
         assert all(c["status"] == 0 for c in got)
         lat = np.array([c["complete_us"] - c["submit_us"] for c in got])
         span = (max(c["complete_us"] for c in got) - min(c["submit_us"] for c in got)) * 1e-6
-        return {"p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
-                "mean_us": round(float(lat.mean()), 1), "gbps": round(total_bytes / span / 1e9, 3),
-                "req_per_s": round(n_req / span, 1)}
+        out = {"p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+               "mean_us": round(float(lat.mean()), 1), "gbps": round(total_bytes / span / 1e9, 3),
+               "req_per_s": round(n_req / span, 1)}
+        if lam is not None:
+            out["offered_req_per_s"] = round(lam, 1)
+            out["submitted_req_per_s"] = round(n_req / t_sub, 1)
+        return out
 
     res = {"requests": n_req, "payloads": len(ps), "mean_payload_mb": round(float(nbytes.mean()) / 1e6, 3),
-           "rho": rho, "hbm_budget_gib": budget >> 30}
+           "hbm_budget_gib": budget >> 30, "fifo": {}, "served": {}}
     cfgs = {"fifo": dict(lanes=1, max_batch=1), "served": dict(lanes=4, max_batch=256)}
-    servers = {k: C.Server(codec, hbm_budget=budget if k == "served" else budget // 2, **v)
-               for k, v in cfgs.items()}
-    sat = {k: run(s, None) for k, s in servers.items()}
-    lam = rho * sat["fifo"]["req_per_s"]
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
-    res["offered_req_per_s"] = round(lam, 1)
-    for k, s in servers.items():
-        res[k] = {"saturation": sat[k], "at_offered_load": run(s, arrivals)}
-        s.close()
+    sat = {}
+    for k, cfg in cfgs.items():
+        srv = C.Server(codec, hbm_budget=budget, **cfg)
+        sat[k] = run(srv, None)
+        res[k]["saturation"] = sat[k]
+        for rho in rhos:
+            res[k][f"rho_{rho}"] = run(srv, rho * sat[k]["req_per_s"])
+        srv.close()
+        torch.cuda.empty_cache()
+    f_sat, s_sat = sat["fifo"]["req_per_s"], sat["served"]["req_per_s"]
+    if s_sat > f_sat:
+        res["between"] = {}
+        for j in (1, 2):
+            lam = f_sat * (s_sat / f_sat) ** (j / 3)
+            row = {}
+            for k, cfg in cfgs.items():
+                srv = C.Server(codec, hbm_budget=budget, **cfg)
+                row[k] = run(srv, lam)
+                srv.close()
+                torch.cuda.empty_cache()
+            res["between"][f"{lam:.0f}_req_per_s"] = row
     return res
 
 
@@ -339,8 +386,12 @@ def float32_case(codec, torch, reps=10):
     ratio, c, d = _device_rates(codec, torch, xd, reps)
     del xd
     torch.cuda.empty_cache()
+    algo = x.nbytes * (1 + ratio)  # values read + stream written (compression), the reverse for decompression
+    ops = {op: {"achieved": round(algo / (x.nbytes / g), 2), "frac": round(algo / (x.nbytes / g) / HBM_PEAK_GBPS, 4)}
+           for op, g in (("compress", c), ("decompress", d))}
     return {"workload": "mixed_f32: 536,870,912 float32 values (2 GiB)", "ratio": ratio,
-            "compress_gbps": c, "decompress_gbps": d, "host_pipeline": host_pipeline(codec, x, torch)}
+            "compress_gbps": c, "decompress_gbps": d, "roofline_ops": ops,
+            "host_pipeline": host_pipeline(codec, x, torch)}
 
 
 def codec_bound(x):
@@ -563,12 +614,167 @@ def studies(codec, torch):
     return res
 
 
+def _kernel_short(name):
+    """Short label of a kernel name as rocprofv3 prints it."""
+    for key, label in (("k_compress_pass<falcon_dev::TF64, 16, 1", "k_compress_pass<size>"),
+                       ("k_compress_pass<falcon_dev::TF64, 16, 2", "k_compress_pass<write>"),
+                       ("k_compress_pass<falcon_dev::TF32, 16, 1", "k_compress_pass<size>"),
+                       ("k_compress_pass<falcon_dev::TF32, 16, 2", "k_compress_pass<write>"),
+                       ("k_compress_queue<", "k_compress_queue"), ("k_compress_pass_mixed<", "k_compress_pass_mixed"),
+                       ("k_decompress_mixed", "k_decompress_mixed"), ("k_decompress<", "k_decompress"),
+                       ("k_scan_tiles", "k_scan_tiles"), ("k_scan_tile_sums", "k_scan_tile_sums"),
+                       ("k_scan_apply", "k_scan_apply"), ("k_fill_u64", "k_fill_u64"),
+                       ("k_batch_headers", "k_batch_headers"), ("k_gather_sizes", "k_gather_sizes")):
+        if key in name:
+            return label
+    return name[:60]
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def trace_summary(path, skip):
+    """Per-kernel durations from a rocprofv3 --kernel-trace CSV, leaving out
+    the first `skip` dispatches of every kernel (the warm-up steps); prints a
+    markdown table (microseconds)."""
+    import numpy as np
+    rows = _read_csv(path)
+    by = {}
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Name")
+        t = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        by.setdefault(name, []).append((int(r["Start_Timestamp"]), t))
+    print(f"Source: `{os.path.basename(path)}`; the first {skip} dispatch(es) of each kernel left out.\n")
+    print("| kernel | full name (truncated) | dispatches | used | average us | median us | min us | max us |")
+    print("|---|---|---|---|---|---|---|---|")
+    out = {}
+    for name, v in sorted(by.items(), key=lambda kv: -sum(t for _, t in kv[1])):
+        v.sort()
+        used = np.array([t for _, t in v[skip:]] or [t for _, t in v])
+        out[_kernel_short(name)] = float(used.mean())
+        print(f"| {_kernel_short(name)} | `{name[:70]}` | {len(v)} | {used.size} | {used.mean():.1f} | "
+              f"{np.median(used):.1f} | {used.min():.1f} | {used.max():.1f} |")
+    return out
+
+
+def traffic_summary(fetch_csv, write_csv, bench_json):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for
+    the plain device copy of the input that bench.py --copy-calibration runs
+    (__amd_rocclr_copyBuffer: the input's bytes read and written), against
+    the algorithmic bytes per launch that the benchmark line lists.  Prints
+    markdown and the JSON record bench.py reads (profiles/hbm_traffic.json)."""
+    import numpy as np
+    with open(bench_json) as f:
+        line = [ln for ln in f if ln.startswith("{")][-1]
+    b = json.loads(line)
+    nbytes = b["config"]["bytes"]
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in _read_csv(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+    fk, wk = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fk if "copyBuffer" in k]
+    cf = max(fk[copy[0]]) if copy else None
+    cw = max(wk[copy[0]]) if copy else None
+    f_fac = nbytes / 1024 / cf if cf else 1.0
+    w_fac = nbytes / 1024 / cw if cw else 1.0
+    rec = {"kernel_digest": kernel_source_digest(), "workload": b["config"]["workload"],
+           "calibration": {"fetch_factor": f_fac, "write_factor": w_fac, "copy_fetch_kib": cf, "copy_write_kib": cw},
+           "kernels": {}}
+    print(f"Calibration: the plain copy of {nbytes:,} bytes reads FETCH_SIZE = {cf:,.1f} KiB and WRITE_SIZE = "
+          f"{cw:,.1f} KiB; scale factors {f_fac:.5f} and {w_fac:.5f}.\n")
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (calibrated) | algorithmic bytes | ratio |")
+    print("|---|---|---|---|---|---|")
+    algo = b.get("kernel_algorithmic_bytes", {})
+    for name in fk:
+        short = _kernel_short(name)
+        if short not in algo:
+            continue
+        fv, wv = float(np.median(fk[name])), float(np.median(wk.get(name, [0.0])))
+        hbm = int(fv * 1024 * f_fac + wv * 1024 * w_fac)
+        rec["kernels"][short] = {"fetch_kib": fv, "write_kib": wv, "hbm_bytes_per_launch": hbm,
+                                 "algorithmic_bytes": algo[short]}
+        print(f"| {short} | {fv:,.1f} | {wv:,.1f} | {hbm:,} | {algo[short]:,} | {hbm / algo[short]:.3f} |")
+    print("\n```json\n" + json.dumps(rec, indent=1) + "\n```")
+    return rec
+
+
+def sweeps(codec, torch, x):
+    """Host pipeline geometry (streams x batch) and compression schedulers x
+    streams on the 2 GiB float64 workload from pinned buffers, and practical
+    HBM ceilings from plain device operations on 2 GiB (a copy, a read-only
+    reduction, a fill), each best of 5 with HIP events."""
+    import numpy as np
+    res = {"pipeline": {}, "schedulers": {}, "hbm_ceilings": {}}
+    xh = torch.from_numpy(x).pin_memory()
+    sbuf = torch.empty(codec_bound(x), dtype=torch.uint8, pin_memory=True)
+    ybuf = torch.empty(x.size, dtype=torch.float64, pin_memory=True)
+
+    def host_rates(reps=2):
+        tc = td = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            s_ = codec.compress_host(xh, out=sbuf)
+            t1 = time.perf_counter()
+            codec.decompress_host(s_, out=ybuf)
+            t2 = time.perf_counter()
+            tc, td = min(tc, t1 - t0), min(td, t2 - t1)
+        return round(x.nbytes / tc / 1e9, 2), round(x.nbytes / td / 1e9, 2)
+    for ns in (1, 2, 4, 8, 16):
+        for bc in (256, 1024, 4096):
+            codec.set_pipeline(ns, bc)
+            c, d = host_rates()
+            res["pipeline"][f"{ns}x{bc}"] = {"compress_gbps": c, "decompress_gbps": d}
+    codec.set_pipeline()
+    for kind in ("event", "sync", "prealloc"):
+        codec.set_scheduler(kind)
+        for ns in (1, 2, 4, 8, 16, 32):
+            codec.set_pipeline(ns, 1024)
+            res["schedulers"][f"{kind}_{ns}"] = host_rates()[0]
+    codec.set_scheduler("event")
+    codec.set_pipeline()
+    # ceilings: a pinned host -> device and device -> host copy, then device ops
+    xd = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(xd)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps=5):
+        best = float("inf")
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            ev[1].synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        return best * 1e-3
+    res["hbm_ceilings"]["h2d_pinned_gbps"] = round(x.nbytes / timed(lambda: xd.copy_(xh, non_blocking=True)) / 1e9, 2)
+    res["hbm_ceilings"]["d2h_pinned_gbps"] = round(x.nbytes / timed(lambda: ybuf.copy_(xd, non_blocking=True)) / 1e9, 2)
+    res["hbm_ceilings"]["copy_gbps (read+write)"] = round(2 * x.nbytes / timed(lambda: yd.copy_(xd)) / 1e9, 1)
+    res["hbm_ceilings"]["read_gbps (sum)"] = round(x.nbytes / timed(lambda: xd.sum()) / 1e9, 1)
+    res["hbm_ceilings"]["write_gbps (fill)"] = round(x.nbytes / timed(lambda: yd.fill_(1.0)) / 1e9, 1)
+    del xh, sbuf, ybuf, xd, yd
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1 << 28, help="values (default: the 2 GiB workload)")
+    ap.add_argument("--n", type=int, default=None, help="values (default: the 2 GiB workload)")
+    ap.add_argument("--workload", choices=("sensor_f64", "mixed_f32"), default="sensor_f64",
+                    help="the workload of the timed steps (default: the 2 GiB float64 sensor series)")
+    ap.add_argument("--form", choices=("two_pass", "single_pass"), default="two_pass",
+                    help="compression form of the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host", action="store_true", help="skip the host -> host pipeline measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 10,000-series batched launch measurement")
@@ -579,10 +785,25 @@ def main():
                     help="also stream the full-length-range 10,000-series batch (about 109 GB) through the GPU")
     ap.add_argument("--studies", action="store_true",
                     help="also run the parameter studies (beta, data size, pipeline batch size)")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="also sweep the host pipeline geometry and schedulers and measure HBM / PCIe ceilings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of the input "
-                         "(2 GiB read + 2 GiB write) as the reference for HBM byte counters")
+                         "(its bytes read and written) as the reference for HBM byte counters")
+    ap.add_argument("--only", choices=("batched", "serving"),
+                    help="run only this section (no timed steps of the main workload); prints its JSON")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="no GPU: summarise a rocprofv3 kernel trace (per-kernel durations) and exit")
+    ap.add_argument("--skip", type=int, default=0, help="--trace-summary: dispatches per kernel to leave out")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="no GPU: HBM bytes per launch from two rocprofv3 counter runs, and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.skip)
+        return
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this codec's multi-GPU "
               "sharding is a design note, not a measured path.", file=sys.stderr)
@@ -593,19 +814,29 @@ def main():
     from paper_2511_04140_amd import codec as C
     from paper_2511_04140_amd import workloads as W
 
+    if args.only:
+        codec = C.Codec(0)
+        res = batched(codec, torch) if args.only == "batched" else serving(codec, torch)
+        codec.close()
+        print(json.dumps({args.only: res}))
+        return
     dev = torch.device("cuda", 0)
-    x = W.sensor_f64(args.n, seed=2)
+    f32 = args.workload == "mixed_f32"
+    n = args.n or (1 << 29 if f32 else 1 << 28)
+    x = W.mixed_f32(n, seed=3) if f32 else W.sensor_f64(n, seed=2)
+    tdt = torch.float32 if f32 else torch.float64
     xd = torch.from_numpy(x).to(dev)
     nbytes = x.nbytes
     codec = C.Codec(0)
-    cap = C.compress_bound(x.size, torch.float64)
+    tcodec = C.Codec(0, form=args.form) if args.form != "two_pass" else codec
+    cap = C.compress_bound(x.size, tdt)
     sbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
     ybuf = torch.empty_like(xd)
 
     # warm-up (first pass also checks the round trip)
     for i in range(args.warmup):
-        s = codec.compress(xd, out=sbuf)
-        y = codec.decompress(s, out=ybuf)
+        s = tcodec.compress(xd, out=sbuf)
+        y = tcodec.decompress(s, out=ybuf)
         if i == 0:
             assert torch.equal(y.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
     torch.cuda.synchronize()
@@ -613,12 +844,12 @@ def main():
     kc, kd, sc, sd_ = [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s = codec.compress(xd, out=sbuf)
-        kc.append(codec.last_kernel_ms())
-        sc.append(codec.last_stage_ms())
-        y = codec.decompress(s, out=ybuf)
-        kd.append(codec.last_kernel_ms())
-        sd_.append(codec.last_stage_ms())
+        s = tcodec.compress(xd, out=sbuf)
+        kc.append(tcodec.last_kernel_ms())
+        sc.append(tcodec.last_stage_ms())
+        y = tcodec.decompress(s, out=ybuf)
+        kd.append(tcodec.last_kernel_ms())
+        sd_.append(tcodec.last_stage_ms())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert torch.equal(ybuf.view(torch.uint8), xd.view(torch.uint8)), "round trip failed"
@@ -631,29 +862,37 @@ def main():
     step_s = (t1 - t0) / args.steps
     kc_ms, kd_ms = float(np.mean(kc)), float(np.mean(kd))
     nc = (x.size + 1024) // 1025
-    # kernels of the path: their average durations (HIP events) and the
-    # algorithmic bytes one launch moves
-    kernels = {
-        "k_compress_pass<size>": (float(np.mean([v[0] for v in sc])), nbytes + 4 * nc),
-        "k_scan (compress)": (float(np.mean([v[1] for v in sc])), 4 * nc + 8 * nc),
-        "k_compress_pass<write>": (float(np.mean([v[2] for v in sc])), nbytes + clen - 4 * nc),
+    # kernels of the path: their average durations over the timed steps (HIP
+    # events on the launch stream) and the algorithmic bytes one launch moves
+    if args.form == "two_pass":
+        kernels = {
+            "k_compress_pass<size>": (float(np.mean([v[0] for v in sc])), nbytes + 4 * nc),
+            "k_scan (compress)": (float(np.mean([v[1] for v in sc])), 4 * nc + 8 * nc),
+            "k_compress_pass<write>": (float(np.mean([v[2] for v in sc])), nbytes + clen - 4 * nc),
+        }
+    else:
+        kernels = {"k_compress_queue": (float(np.mean([v[0] for v in sc])), nbytes + clen)}
+    kernels.update({
         "k_scan (decompress)": (float(np.mean([v[1] for v in sd_])), 4 * nc + 8 * nc),
         "k_decompress": (float(np.mean([v[2] for v in sd_])), clen + nbytes),
-    }
+    })
     dominant = max(kernels, key=lambda k: kernels[k][0])
     dom_ms, dom_bytes = kernels[dominant]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dominant, dom_bytes)
-    algo_c = nbytes + clen          # read the values, write the stream
-    algo_d = clen + nbytes          # read the stream, write the values
+    traffic = measured_traffic(dominant, dom_bytes) if args.workload == "sensor_f64" else None
+    algo = nbytes + clen  # compression: values read, stream written; decompression the reverse
 
-    # fraction of chunks in each case of Eq. 3 (header byte alpha_max <= 22)
+    # fraction of chunks in each case of Eq. 3 (header bytes alpha_max, beta_hat_max)
     sizes = s[32:32 + 4 * nc].view(torch.int32).to(torch.int64)
     offs = torch.cumsum(sizes, 0) - sizes
     a_bytes = s[32 + 4 * nc + offs]
     b_bytes = s[32 + 4 * nc + offs + 1]
-    case1 = float(((a_bytes <= 22) & (b_bytes <= 15)).float().mean().item())
+    amax, bmax = (10, 6) if f32 else (22, 15)
+    case1 = float(((a_bytes <= amax) & (b_bytes <= bmax)).float().mean().item())
 
+    workload = WORKLOAD if not f32 else ("mixed_f32: 536,870,912 float32 values (2 GiB): half sinusoid + "
+                                         "N(0, 0.01^2) noise at 0-4 decimal places, half 512^3 interpolated "
+                                         "fields at full precision")
     out = {
         "metric": METRIC,
         "value": round(nbytes / step_s / 1e9, 3),
@@ -665,15 +904,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": int(x.size), "bytes": int(nbytes),
-                   "chunk": 1025, "resident": "HBM"},
+        "config": {"workload": workload, "n": int(x.size), "bytes": int(nbytes),
+                   "chunk": 1025, "resident": "HBM", "compression_form": args.form},
         "compress_gbps": round(nbytes / (kc_ms * 1e-3) / 1e9, 3),
         "decompress_gbps": round(nbytes / (kd_ms * 1e-3) / 1e9, 3),
         "ratio": round(ratio, 6),
         "case1_chunk_fraction": round(case1, 6),
         "kernel_ms": {k: round(v[0], 4) for k, v in kernels.items()},
+        "kernel_algorithmic_bytes": {k.split(" ")[0]: int(v[1]) for k, v in kernels.items() if "scan" not in k},
         "roofline": {
             "bound": "hbm",
             "kernel": dominant,
@@ -685,21 +925,23 @@ def main():
             "algorithmic_bytes": int(dom_bytes),
         },
         "roofline_ops": {
-            "compress (size pass + scan + write pass)": {
-                "ms": round(kc_ms, 4), "achieved": round(algo_c / (kc_ms * 1e-3) / 1e9, 2),
-                "frac": round(algo_c / (kc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
-            "decompress (decoding kernel)": {
-                "ms": round(kd_ms, 4), "achieved": round(algo_d / (kd_ms * 1e-3) / 1e9, 2),
-                "frac": round(algo_d / (kd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+            "compress (all launches)": {
+                "ms": round(kc_ms, 4), "achieved": round(algo / (kc_ms * 1e-3) / 1e9, 2),
+                "frac": round(algo / (kc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+            "decompress (scan + decoding kernel)": {
+                "ms": round(kd_ms, 4), "achieved": round(algo / (kd_ms * 1e-3) / 1e9, 2),
+                "frac": round(algo / (kd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         },
     }
     del sbuf, ybuf, s, y, xd
+    if tcodec is not codec:
+        tcodec.close()
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     log(f"device round trip: {out['value']} GB/s")
     if not args.no_host:
         out["host_pipeline"] = host_pipeline(codec, x, torch)
         log(f"host pipeline: {out['host_pipeline']}")
-    if not args.no_float32:
+    if not args.no_float32 and not f32:
         out["float32"] = float32_case(codec, torch)
         log(f"float32: {out['float32']}")
     if not args.no_batched:
@@ -710,7 +952,7 @@ def main():
         out["serving"] = serving(codec, torch)
         torch.cuda.empty_cache()
         log(f"serving: {out['serving']}")
-    if not args.no_ablation:
+    if not args.no_ablation and not f32:
         out["ablation"] = ablation(codec, torch, x)
         log(f"ablation: {out['ablation']}")
     if args.full_range:
@@ -718,8 +960,15 @@ def main():
     if args.studies:
         out["studies"] = studies(codec, torch)
         torch.cuda.empty_cache()
+    if args.sweeps and not f32:
+        out["sweeps"] = sweeps(codec, torch, x)
+        log(f"sweeps: {out['sweeps']}")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x)
+        x32 = None if f32 else W.mixed_f32(1 << 24, seed=3, side=128)
+        out["cpu_baseline"] = cpu_baseline(x, x32)
+        if x32 is not None:
+            out["cpu_baseline"]["float32"]["sample"] = ("mixed_f32 at 2^24 values (the same composition: half "
+                                                       "low-precision sinusoid, half 128^3 fields)")
         out["cpu_baseline"]["small_case"] = oracle_small_case()
     codec.close()
     print(json.dumps(out))
