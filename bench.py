@@ -278,7 +278,7 @@ def batched(codec, torch, reps=5):
                      "batched_gbps": round(raw / t_plan / 1e9, 3),
                      "speedup": round(t_loop / t_plan, 2),
                      "batched_hbm_frac": frac(t_plan), "per_series_hbm_frac": frac(t_loop),
-                     "plan": {k: info[k] for k in ("split", "waves_per_group", "grid_percent", "candidates")}},
+                     "plan": {k: info[k] for k in ("split", "waves_per_group", "grid_percent", "candidates", "form")}},
         "decompress": {"per_series_gbps": round(raw / t_dloop / 1e9, 3),
                        "batched_gbps": round(raw / t_dplan / 1e9, 3),
                        "speedup": round(t_dloop / t_dplan, 2),

@@ -304,9 +304,18 @@ typedef struct falcon_series {
 typedef enum { FALCON_OP_COMPRESS = 0, FALCON_OP_DECOMPRESS = 1 } falcon_op;
 
 /* Plan flags: FALCON_PLAN_TUNE times every launch geometry candidate on the
- * plan's own series and keeps the fastest; FALCON_PLAN_GRAPH records the
- * plan's launches as one HIP graph replayed by falcon_plan_run. */
-enum { FALCON_PLAN_TUNE = 1, FALCON_PLAN_GRAPH = 2 };
+ * plan's own series and keeps the fastest (compression: launch form split /
+ * mixed x 8 or 16 waves per workgroup x full or half grid x two passes with
+ * static striding or the single pass with its work queue; decompression:
+ * form x grid), and records the choice in the context by shape class
+ * (operation, dtypes present, log2 of the chunk count, log2 of the series
+ * count): a later tuned plan of the same class takes the recorded geometry
+ * without timing.  FALCON_PLAN_GRAPH records the plan's launches as one HIP
+ * graph replayed by falcon_plan_run.  FALCON_PLAN_SINGLE_PASS makes an
+ * untuned compression plan run the single-pass form (the tuner decides by
+ * itself).  The one-shot batch calls compress in the context's
+ * falcon_compress_form. */
+enum { FALCON_PLAN_TUNE = 1, FALCON_PLAN_GRAPH = 2, FALCON_PLAN_SINGLE_PASS = 4 };
 
 typedef struct falcon_plan falcon_plan;
 
@@ -319,6 +328,9 @@ typedef struct falcon_plan_info {
   float default_ms;     /* autotuner: time of the default geometry */
   int graph;            /* 1 if runs replay a HIP graph */
   uint64_t total_chunks;
+  int form;             /* compression: 0 two passes, 1 single pass (work queue; falcon_compress_form) */
+  int from_cache;       /* 1 if the geometry came from the context's record of an earlier plan of the
+                           same shape class instead of timing */
 } falcon_plan_info;
 
 /* The one-series-per-launch path over count series, as a C loop: one

@@ -41,7 +41,8 @@ class PlanInfo(ctypes.Structure):
     """falcon_plan_info of falcon.h."""
     _fields_ = [("split", ctypes.c_int), ("waves_per_group", ctypes.c_int), ("grid_percent", ctypes.c_int),
                 ("candidates", ctypes.c_int), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
-                ("graph", ctypes.c_int), ("total_chunks", ctypes.c_uint64)]
+                ("graph", ctypes.c_int), ("total_chunks", ctypes.c_uint64), ("form", ctypes.c_int),
+                ("from_cache", ctypes.c_int)]
 
 
 class Opts(ctypes.Structure):
@@ -74,6 +75,7 @@ OP_COMPRESS = 0
 OP_DECOMPRESS = 1
 PLAN_TUNE = 1
 PLAN_GRAPH = 2
+PLAN_SINGLE_PASS = 4
 SCHEDULERS = {"event": 0, "sync": 1, "prealloc": 2}
 # ablation variants of compression (Sec. 5.4.2)
 VARIANTS = {"falcon": 0, "elf": 1, "sparse": 2, "dense": 3}
@@ -466,9 +468,9 @@ class Codec:
             raise FalconError(st, "falcon_decompress_batch")
         return views
 
-    def plan_compress(self, xs, outs=None, tune=True, graph=True):
+    def plan_compress(self, xs, outs=None, tune=True, graph=True, single_pass=False):
         descs, views = self._compress_descs(xs, outs)
-        return Plan(self, OP_COMPRESS, descs, views, tune, graph)
+        return Plan(self, OP_COMPRESS, descs, views, tune, graph, single_pass)
 
     def plan_decompress(self, streams, counts, dtypes, outs=None, tune=True, graph=True):
         descs, views = self._decompress_descs(streams, counts, dtypes, outs)
@@ -479,10 +481,10 @@ class Plan:
     """A reusable batch launch (falcon_plan): fixed series buffers, tuned
     geometry, optionally replayed as a HIP graph."""
 
-    def __init__(self, codec: Codec, op: int, descs, views, tune: bool, graph: bool):
+    def __init__(self, codec: Codec, op: int, descs, views, tune: bool, graph: bool, single_pass: bool = False):
         self.codec, self.op, self.descs, self.views = codec, op, descs, views
         self._p = ctypes.c_void_p()
-        flags = (PLAN_TUNE if tune else 0) | (PLAN_GRAPH if graph else 0)
+        flags = (PLAN_TUNE if tune else 0) | (PLAN_GRAPH if graph else 0) | (PLAN_SINGLE_PASS if single_pass else 0)
         st = lib().falcon_plan_create(codec._ctx, op, descs, len(descs), flags, ctypes.byref(self._p))
         if st != 0:
             raise FalconError(st, "falcon_plan_create")

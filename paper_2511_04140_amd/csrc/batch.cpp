@@ -12,7 +12,9 @@
 //
 // Compression runs in two passes over all series (size pass, one scan of
 // all chunk sizes, write pass; see codec_kernels.hpp), so no chunk waits on
-// another.  A run never depends on host state beyond its descriptors: the
+// another, or, when the autotuner finds it faster, in the single pass with a
+// work queue over all chunks and a look-back that stops at each series'
+// first chunk.  A run never depends on host state beyond its descriptors: the
 // control block is cleared by a fill kernel at the start of a decompression
 // run (no memset nodes in a recorded graph) and the launch epoch is fixed.
 #include <hip/hip_runtime.h>
@@ -56,7 +58,7 @@ falcon_status grow(P** p, size_t* cap, size_t need, size_t elem, bool pinned, hi
 }
 
 int grid_of(const falcon_ctx* ctx, const BatchGeom& g, int form, int pass, uint64_t chunks, bool compress) {
-  const int maxg = compress ? max_grid_c(ctx, form, pass, g.nw) : max_grid_d(ctx, form);
+  const int maxg = !compress ? max_grid_d(ctx, form) : g.form ? max_grid_q(ctx, form, g.nw) : max_grid_c(ctx, form, pass, g.nw);
   int grid = (int)((int64_t)maxg * g.grid_pct / 100);
   if (grid < 1) grid = 1;
   const int per = compress ? g.nw : kDecompressWaves;
@@ -146,6 +148,10 @@ falcon_status batch_layout(BatchScratch& b, int op, const falcon_series* s, size
   if (op == FALCON_OP_COMPRESS && (r = grow(&b.meta, &b.meta_cap, t ? t : 1, sizeof(ChunkMeta), false, st)) !=
                                       FALCON_OK)
     return r;
+  if (op == FALCON_OP_COMPRESS &&
+      (r = grow(&b.status, &b.status_cap, (size_t)kQueueGroups * kQueueStride + (t ? t : 1), 8, false, st)) !=
+          FALCON_OK)
+    return r;
   if (!b.ctl) {
     if (hipMalloc(&b.ctl, 64) != hipSuccess) return FALCON_ERR_OUT_OF_MEMORY;
     if (launch_fill_u64(reinterpret_cast<uint64_t*>(b.ctl), 8, 0, st) != hipSuccess) return FALCON_ERR_DEVICE;
@@ -169,8 +175,7 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     if (L.has32) parts[np++] = {1, L.t64, L.total - L.t64};
   }
   if (L.op == FALCON_OP_COMPRESS) {
-    // two passes over all series: sizes, one scan over all chunks, writes
-    if (np == 0) parts[np++] = {2, 0, 0};  // only empty series: the write pass writes their headers
+    if (np == 0) parts[np++] = {2, 0, 0};  // only empty series: the last launch writes their headers
     CompressArgs a{};
     a.one = L.one_c;
     a.many = static_cast<const CompressSeries*>(b.many);
@@ -180,6 +185,33 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
     a.gsizes = b.sizes;
     a.offsets = b.offsets;
     a.relative = 1;
+    if (g.form == 1) {
+      // single pass: a work queue and a per-series look-back; counters,
+      // status words and the error word cleared by fill kernels (a recorded
+      // graph replays them), so every run uses the same tag
+      const size_t nq = (size_t)kQueueGroups * kQueueStride;
+      if ((st = dev_err(launch_fill_u64(b.status, nq + (L.total ? L.total : 1), 0, s))) != FALCON_OK ||
+          (st = dev_err(launch_fill_u64(reinterpret_cast<uint64_t*>(b.ctl), 1, 0, s))) != FALCON_OK)
+        return st;
+      a.qctr = b.status;
+      a.status = b.status + nq;
+      a.ctl = b.ctl;
+      a.qtag = kBatchEpoch;
+      for (int i = 0; i < np; ++i) {
+        // launches run one after the other on s: each starts with cleared counters
+        if (i > 0 && (st = dev_err(launch_fill_u64(b.status, nq, 0, s))) != FALCON_OK) return st;
+        a.total_chunks = parts[i].chunks;
+        a.t0 = parts[i].t0;
+        const int grid = grid_of(ctx, g, parts[i].form, 0, parts[i].chunks, true);
+        a.total_waves = (uint32_t)(grid * g.nw);
+        a.qgroups = (uint32_t)(grid < kQueueGroups ? grid : kQueueGroups);
+        if ((st = dev_err(launch_compress_queue(a, parts[i].form, g.nw, grid, s))) != FALCON_OK) return st;
+      }
+      if ((st = dev_err(hipMemcpyAsync(b.h_lens, b.lens, L.count * 8, hipMemcpyDeviceToHost, s))) != FALCON_OK)
+        return st;
+      return dev_err(hipMemcpyAsync(b.h_lens + L.count, b.ctl, 8, hipMemcpyDeviceToHost, s));
+    }
+    // two passes over all series: sizes, one scan over all chunks, writes
     for (int pass = 1; pass <= 2; ++pass) {
       for (int i = 0; i < np; ++i) {
         if (pass == 1 && parts[i].chunks == 0) continue;
@@ -194,7 +226,9 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
                                           s))) != FALCON_OK)
         return st;
     }
-    return dev_err(hipMemcpyAsync(b.h_lens, b.lens, L.count * 8, hipMemcpyDeviceToHost, s));
+    if ((st = dev_err(hipMemcpyAsync(b.h_lens, b.lens, L.count * 8, hipMemcpyDeviceToHost, s))) != FALCON_OK)
+      return st;
+    return dev_err(hipMemcpyAsync(b.h_lens + L.count, b.ctl, 8, hipMemcpyDeviceToHost, s));
   }
   // clear the control block (error word) of decompression
   if ((st = dev_err(launch_fill_u64(reinterpret_cast<uint64_t*>(b.ctl), 2, 0, s))) != FALCON_OK) return st;
@@ -225,11 +259,11 @@ falcon_status batch_enqueue(const falcon_ctx* ctx, BatchScratch& b, const BatchL
 
 falcon_status batch_result(const BatchScratch& b, const BatchLayout& L, const falcon_series* src,
                            falcon_series* dst) {
-  if (L.op == FALCON_OP_DECOMPRESS) {
-    uint32_t err;
-    memcpy(&err, b.h_lens + L.count, 4);
-    if (err == kBatchEpoch) return FALCON_ERR_CORRUPT_STREAM;
-  }
+  uint32_t err[2];
+  memcpy(err, b.h_lens + L.count, 8);
+  if (L.op == FALCON_OP_DECOMPRESS && err[0] == kBatchEpoch) return FALCON_ERR_CORRUPT_STREAM;
+  // a single-pass look-back that gave up (never in a correct run)
+  if (L.op == FALCON_OP_COMPRESS && err[1] != 0) return FALCON_ERR_DEVICE;
   if (dst)
     for (size_t i = 0; i < L.count; ++i) dst[i].out_len = L.op == FALCON_OP_COMPRESS ? b.h_lens[i] : src[i].n;
   return FALCON_OK;
@@ -245,6 +279,7 @@ void batch_free(BatchScratch& b) {
   if (b.ctl) (void)hipFree(b.ctl);
   if (b.lens) (void)hipFree(b.lens);
   if (b.h_lens) (void)hipHostFree(b.h_lens);
+  if (b.status) (void)hipFree(b.status);
   b = BatchScratch();
 }
 
@@ -260,6 +295,7 @@ struct falcon_plan {
   BatchGeom geom;
   hipStream_t stream = nullptr;
   int candidates = 0;
+  bool from_cache = false;
   float best_ms = 0.f, default_ms = 0.f;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -301,22 +337,51 @@ falcon_status time_runs(falcon_plan* p, int reps, float* best) {
   return st;
 }
 
-// Autotuner: times every launch form x workgroup size x grid fraction on
-// the plan's own series and keeps the fastest.  All candidates produce the
-// same bytes (the launch geometry never changes a stream).
+// Shape class of a plan for the tuning record: operation, dtypes present,
+// log2 of the chunk count and of the series count.
+uint64_t shape_class(const BatchLayout& L) {
+  auto lg = [](uint64_t v) {
+    uint64_t k = 0;
+    while (v > 1) {
+      v >>= 1;
+      ++k;
+    }
+    return k;
+  };
+  return (uint64_t)L.op | (uint64_t)L.has64 << 1 | (uint64_t)L.has32 << 2 | lg(L.total + 1) << 3 |
+         lg(L.count) << 16;
+}
+
+// Autotuner: times every candidate geometry on the plan's own series and
+// keeps the fastest.  Compression: launch form (split / mixed) x 16 or 8
+// waves per workgroup x full or half grid x two passes (static striding) or
+// single pass (work queue); decompression: launch form x grid.  All
+// candidates produce the same bytes (the launch geometry never changes a
+// stream).  The choice is recorded in the context by shape class, and a
+// later plan of the same class takes it without timing.
 falcon_status autotune(falcon_plan* p) {
+  const uint64_t key = shape_class(p->layout);
+  auto hit = p->ctx->tuned.find(key);
+  if (hit != p->ctx->tuned.end()) {
+    p->geom = hit->second;
+    p->from_cache = true;
+    return FALCON_OK;
+  }
   std::vector<BatchGeom> cands;
   const bool both = p->layout.has64 && p->layout.has32;
-  for (int split = 1; split >= (both ? 0 : 1); --split)
-    for (int nw : {16, 8})
-      for (int pct : {100, 50}) {
-        if (p->layout.op == FALCON_OP_DECOMPRESS && nw != 16) continue;  // no workgroup size choice there
-        BatchGeom g;
-        g.split = split;
-        g.nw = nw;
-        g.grid_pct = pct;
-        cands.push_back(g);
-      }
+  const bool comp = p->layout.op == FALCON_OP_COMPRESS;
+  for (int form = 0; form <= (comp ? 1 : 0); ++form)
+    for (int split = 1; split >= (both ? 0 : 1); --split)
+      for (int nw : {16, 8})
+        for (int pct : {100, 50}) {
+          if (!comp && nw != 16) continue;  // no workgroup size choice there
+          BatchGeom g;
+          g.split = split;
+          g.nw = nw;
+          g.grid_pct = pct;
+          g.form = form;
+          cands.push_back(g);
+        }
   float best = 1e30f;
   BatchGeom pick = cands[0];
   for (size_t i = 0; i < cands.size(); ++i) {
@@ -333,6 +398,7 @@ falcon_status autotune(falcon_plan* p) {
   p->geom = pick;
   p->best_ms = best;
   p->candidates = (int)cands.size();
+  p->ctx->tuned[key] = pick;
   return FALCON_OK;
 }
 
@@ -349,8 +415,10 @@ falcon_status batch_call(falcon_ctx* ctx, int op, falcon_series* s, size_t count
   if (hipSetDevice(ctx->device) != hipSuccess) return FALCON_ERR_DEVICE;
   hipStream_t hs = stream ? static_cast<hipStream_t>(stream) : ctx->main.stream;
   BatchLayout L;
+  BatchGeom g;
+  g.form = op == FALCON_OP_COMPRESS ? ctx->compress_form : 0;
   falcon_status st = batch_layout(ctx->batch, op, s, count, L, hs);
-  if (st == FALCON_OK) st = batch_enqueue(ctx, ctx->batch, L, BatchGeom(), hs, true);
+  if (st == FALCON_OK) st = batch_enqueue(ctx, ctx->batch, L, g, hs, true);
   if (st == FALCON_OK) st = dev_err(hipStreamSynchronize(hs));
   if (st == FALCON_OK) st = batch_result(ctx->batch, L, s, s);
   return st;
@@ -383,6 +451,7 @@ falcon_status falcon_plan_create(falcon_ctx* ctx, falcon_op op, const falcon_ser
     st = dev_err(hipMemcpyAsync(p->scratch.many, p->scratch.h_desc, p->layout.desc_bytes, hipMemcpyHostToDevice,
                                 p->stream));
   if (st == FALCON_OK) st = dev_err(hipStreamSynchronize(p->stream));
+  if (op == FALCON_OP_COMPRESS && (flags & FALCON_PLAN_SINGLE_PASS)) p->geom.form = 1;
   if (st == FALCON_OK && (flags & FALCON_PLAN_TUNE)) st = autotune(p);
   if (st == FALCON_OK && (flags & FALCON_PLAN_GRAPH)) {
     if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -424,6 +493,8 @@ falcon_status falcon_plan_describe(const falcon_plan* p, falcon_plan_info* info)
   info->default_ms = p->default_ms;
   info->graph = p->exec != nullptr;
   info->total_chunks = p->layout.total;
+  info->form = p->layout.op == FALCON_OP_COMPRESS ? p->geom.form : 0;
+  info->from_cache = p->from_cache ? 1 : 0;
   return FALCON_OK;
 }
 

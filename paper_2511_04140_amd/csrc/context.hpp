@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <map>
 #include <vector>
 
 #include "../../include/falcon.h"
@@ -80,6 +81,7 @@ struct BatchGeom {
   int split = 1;
   int nw = falcon_dev::kCompressWaves;
   int grid_pct = 100;
+  int form = 0;  // compression: 0 two passes (static striding), 1 single pass (work queue, look-back)
 };
 
 // Where a batch's series sit in launch-chunk space (float64 series first).
@@ -113,6 +115,8 @@ struct BatchScratch {
   size_t lens_cap = 0;
   uint64_t* h_lens = nullptr;    // pinned: lengths, then the error word
   size_t h_lens_cap = 0;
+  uint64_t* status = nullptr;    // single-pass compression: ticket counters, then one status word per chunk
+  size_t status_cap = 0;
 };
 
 }  // namespace falcon_host
@@ -167,6 +171,8 @@ struct falcon_ctx {
   std::vector<falcon_host::PipeLane> pipe;
   // one-shot batch calls
   falcon_host::BatchScratch batch;
+  // geometries the plan autotuner chose, by shape class (see batch.cpp)
+  std::map<uint64_t, falcon_host::BatchGeom> tuned;
 };
 
 namespace falcon_host {
