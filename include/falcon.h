@@ -389,6 +389,10 @@ void falcon_plan_destroy(falcon_plan* p);
  * one-request-per-launch FIFO. */
 typedef struct falcon_server falcon_server;
 
+/* Each lane also keeps the scratch of its batch launches (descriptors, chunk
+ * sizes, offsets and metadata: about 36 bytes per chunk) outside the pool; a
+ * batch takes requests only up to 2^22 chunks (at least one request), so this
+ * stays below about 150 MB per lane. */
 typedef struct falcon_server_opts {
   size_t hbm_budget;  /* bytes of the output pool (0: 64 GiB) */
   void* pool;         /* optional caller-owned device memory of hbm_budget bytes to use as the pool
@@ -411,7 +415,11 @@ typedef struct falcon_completion {
   falcon_status status;
   void* d_out;        /* in the server's pool: the stream (compress) or the values; null on error */
   size_t out_len;     /* stream bytes (compress) or values (decompress) */
-  double submit_us, admit_us, complete_us;  /* times since the server was created */
+  double submit_us, admit_us, complete_us;  /* host times since the server was created */
+  double dev_start_us, dev_end_us;  /* device times (HIP events) of the start and end of the batch launch the
+                                       request ran in, since a reference event recorded at server creation;
+                                       -1 when it ran in no batch (an error found on the host) */
+  int lane;           /* the lane (stream) of that batch, -1 if none */
 } falcon_completion;
 
 /* Creates a server on ctx (opts may be NULL).  The input buffers of a

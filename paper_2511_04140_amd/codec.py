@@ -68,7 +68,8 @@ class Request(ctypes.Structure):
 class Completion(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("d_out", ctypes.c_void_p),
                 ("out_len", ctypes.c_size_t), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
-                ("complete_us", ctypes.c_double)]
+                ("complete_us", ctypes.c_double), ("dev_start_us", ctypes.c_double),
+                ("dev_end_us", ctypes.c_double), ("lane", ctypes.c_int)]
 
 
 OP_COMPRESS = 0
@@ -558,7 +559,8 @@ class Server:
             c = self._buf[i]
             out.append({"tag": c.tag, "status": c.status, "d_out": c.d_out,
                         "offset": (c.d_out - base) if c.d_out else None, "out_len": c.out_len,
-                        "submit_us": c.submit_us, "admit_us": c.admit_us, "complete_us": c.complete_us})
+                        "submit_us": c.submit_us, "admit_us": c.admit_us, "complete_us": c.complete_us,
+                        "dev_start_us": c.dev_start_us, "dev_end_us": c.dev_end_us, "lane": c.lane})
         return out
 
     def view(self, comp: dict, dtype: torch.dtype = torch.uint8) -> torch.Tensor:

@@ -107,7 +107,8 @@ struct Req {
 
 struct ServeLane {
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev_start = nullptr;  // before the batch's launches
+  hipEvent_t ev = nullptr;        // after them
   BatchScratch scratch;
   BatchLayout layout;
   std::vector<Req> reqs;       // the batch in flight
@@ -136,6 +137,7 @@ struct falcon_server {
   // worker-only state
   std::deque<Req> pending, admitted;
   std::atomic<uint64_t> in_flight{0};
+  hipEvent_t ev_ref = nullptr;  // device time origin of the batch intervals
 
   double now_us() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
 };
@@ -147,8 +149,16 @@ size_t output_bytes(const falcon_request& r) {
   return r.n * elem_size(r.dtype);
 }
 
-void complete(falcon_server* S, const Req& q, falcon_status st, size_t out_len) {
+// A batch holds at most this many chunks, so that a lane's batch scratch
+// (about 36 bytes per chunk, outside the pool) stays below about 150 MB.
+constexpr uint64_t kLaneChunkCap = 1ull << 22;
+
+void complete(falcon_server* S, const Req& q, falcon_status st, size_t out_len, int lane = -1,
+              double dev_start = -1.0, double dev_end = -1.0) {
   falcon_completion c{};
+  c.lane = lane;
+  c.dev_start_us = dev_start;
+  c.dev_end_us = dev_end;
   c.tag = q.r.tag;
   c.status = st;
   c.d_out = st == FALCON_OK ? q.out : nullptr;
@@ -181,11 +191,15 @@ void launch_batch(falcon_server* S, ServeLane& L) {
   const int op = S->admitted.front().r.op;
   L.reqs.clear();
   L.series.clear();
+  uint64_t chunks = 0;
   for (auto it = S->admitted.begin(); it != S->admitted.end() && (int)L.reqs.size() < S->opts.max_batch;) {
     if (it->r.op != op) {
       ++it;
       continue;
     }
+    const uint64_t nc = chunks_of(it->r.n);
+    if (!L.reqs.empty() && chunks + nc > kLaneChunkCap) break;
+    chunks += nc;
     const falcon_series s = to_series(*it);
     const falcon_status st = batch_check(op, s);
     if (st != FALCON_OK) {
@@ -198,6 +212,7 @@ void launch_batch(falcon_server* S, ServeLane& L) {
   }
   if (L.reqs.empty()) return;
   falcon_status st = batch_layout(L.scratch, op, L.series.data(), L.series.size(), L.layout, L.stream);
+  if (st == FALCON_OK) st = dev_err(hipEventRecord(L.ev_start, L.stream));
   if (st == FALCON_OK) st = batch_enqueue(S->ctx, L.scratch, L.layout, BatchGeom(), L.stream, true);
   if (st == FALCON_OK) st = dev_err(hipEventRecord(L.ev, L.stream));
   if (st != FALCON_OK) {
@@ -215,7 +230,14 @@ void finish_batch(falcon_server* S, ServeLane& L) {
   L.busy = false;
   falcon_status st = batch_result(L.scratch, L.layout, L.series.data(), L.series.data());
   if (st == FALCON_OK) {
-    for (size_t i = 0; i < L.reqs.size(); ++i) complete(S, L.reqs[i], FALCON_OK, L.series[i].out_len);
+    // the batch's device interval, from the server's time origin
+    float a = -1.f, b = -1.f;
+    const int lane = (int)(&L - S->lanes.data());
+    if (hipEventElapsedTime(&a, S->ev_ref, L.ev_start) != hipSuccess ||
+        hipEventElapsedTime(&b, S->ev_ref, L.ev) != hipSuccess)
+      a = b = -1.f;
+    for (size_t i = 0; i < L.reqs.size(); ++i)
+      complete(S, L.reqs[i], FALCON_OK, L.series[i].out_len, lane, a * 1e3, b * 1e3);
   } else if (st == FALCON_ERR_CORRUPT_STREAM && L.reqs.size() > 1) {
     for (size_t i = 0; i < L.reqs.size(); ++i) {
       BatchLayout one;
@@ -327,10 +349,15 @@ falcon_status falcon_server_create(falcon_ctx* ctx, const falcon_server_opts* op
   S->lanes.resize((size_t)o.lanes);
   for (auto& L : S->lanes) {
     if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreate(&L.ev_start) != hipSuccess || hipEventCreate(&L.ev) != hipSuccess) {
       falcon_server_destroy(S);
       return FALCON_ERR_DEVICE;
     }
+  }
+  if (hipEventCreate(&S->ev_ref) != hipSuccess || hipEventRecord(S->ev_ref, S->lanes[0].stream) != hipSuccess ||
+      hipEventSynchronize(S->ev_ref) != hipSuccess) {
+    falcon_server_destroy(S);
+    return FALCON_ERR_DEVICE;
   }
   S->worker = std::thread(worker_main, S);
   *out = S;
@@ -386,9 +413,11 @@ void falcon_server_destroy(falcon_server* S) {
   for (auto& L : S->lanes) {
     if (L.stream) (void)hipStreamSynchronize(L.stream);
     batch_free(L.scratch);
+    if (L.ev_start) (void)hipEventDestroy(L.ev_start);
     if (L.ev) (void)hipEventDestroy(L.ev);
     if (L.stream) (void)hipStreamDestroy(L.stream);
   }
+  if (S->ev_ref) (void)hipEventDestroy(S->ev_ref);
   S->pool.destroy();
   delete S;
 }

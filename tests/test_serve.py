@@ -164,3 +164,33 @@ def test_corrupt_request_fails_alone(codec, orc):
             assert got[i]["status"] == 0
             assert np.array_equal(vals[i].view(np.uint8), xs[i].view(np.uint8))
     srv.close()
+
+
+def test_batches_overlap_on_the_device(codec, orc):
+    """Continuous batching overlaps work on the device: with four lanes and
+    one request per batch, some batch starts on one lane (device clock, HIP
+    events) before a batch on another lane has ended.  Every result is still
+    the oracle's."""
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    xs = [W.sensor_f64(2_000_000 + 1000 * i, seed=700 + i) for i in range(16)]
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    srv = C.Server(codec, hbm_budget=1 << 30, lanes=4, max_batch=1)
+    keep = {}
+    for i, x in enumerate(xd):
+        srv.submit_compress(x, tag=i)
+    got = _drain(srv, len(xd), release=False)
+    for i, x in enumerate(xs):
+        c = got[i]
+        assert c["status"] == 0 and c["lane"] >= 0 and 0 <= c["dev_start_us"] < c["dev_end_us"]
+        assert srv.view(c)[: c["out_len"]].cpu().numpy().tobytes() == orc.compress(x), i
+        keep[i] = c
+    spans = sorted((c["dev_start_us"], c["dev_end_us"], c["lane"]) for c in keep.values())
+    overlaps = [(a, b) for a in spans for b in spans
+                if a[2] != b[2] and a[0] < b[0] < a[1]]
+    _log(f"[serve] {len(overlaps)} overlapping batch pairs on different lanes; spans {spans[:6]}")
+    assert overlaps, "no batch started while another lane's batch was still running"
+    assert len({c["lane"] for c in keep.values()}) > 1
+    for c in keep.values():
+        srv.release(c)
+    srv.close()
