@@ -636,10 +636,11 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
-def trace_summary(path, skip):
+def trace_summary(path, skip, last=0):
     """Per-kernel durations from a rocprofv3 --kernel-trace CSV, leaving out
-    the first `skip` dispatches of every kernel (the warm-up steps); prints a
-    markdown table (microseconds)."""
+    the first `skip` dispatches of every kernel (the warm-up steps), or
+    keeping only the last `last` ones; prints a markdown table
+    (microseconds)."""
     import numpy as np
     rows = _read_csv(path)
     by = {}
@@ -647,17 +648,47 @@ def trace_summary(path, skip):
         name = r.get("Kernel_Name") or r.get("Name")
         t = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
         by.setdefault(name, []).append((int(r["Start_Timestamp"]), t))
-    print(f"Source: `{os.path.basename(path)}`; the first {skip} dispatch(es) of each kernel left out.\n")
+    if last:
+        print(f"Source: `{os.path.basename(path)}`; the last {last} dispatch(es) of each kernel.\n")
+    else:
+        print(f"Source: `{os.path.basename(path)}`; the first {skip} dispatch(es) of each kernel left out.\n")
     print("| kernel | full name (truncated) | dispatches | used | average us | median us | min us | max us |")
     print("|---|---|---|---|---|---|---|---|")
     out = {}
     for name, v in sorted(by.items(), key=lambda kv: -sum(t for _, t in kv[1])):
         v.sort()
-        used = np.array([t for _, t in v[skip:]] or [t for _, t in v])
+        sel = v[-last:] if last else v[skip:]
+        used = np.array([t for _, t in sel] or [t for _, t in v])
         out[_kernel_short(name)] = float(used.mean())
         print(f"| {_kernel_short(name)} | `{name[:70]}` | {len(v)} | {used.size} | {used.mean():.1f} | "
               f"{np.median(used):.1f} | {used.min():.1f} | {used.max():.1f} |")
     return out
+
+
+def counter_summary(path, chunks):
+    """Instruction and wait counters per chunk from a rocprofv3 --pmc CSV of
+    SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS, SQ_WAVE_CYCLES, SQ_WAIT_ANY
+    and SQ_WAVES (one dispatch per kernel, `chunks` chunks); prints markdown.
+    The VALU floor is the time the SIMDs need to issue those VALU
+    instructions alone (4 cycles per wave64 instruction at 2.4 GHz on 1,024
+    SIMDs)."""
+    acc = {}
+    for r in _read_csv(path):
+        k = _kernel_short(r["Kernel_Name"])
+        d = acc.setdefault((k, r.get("Dispatch_Id")), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    print(f"Per chunk ({chunks:,} chunks per dispatch); wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES.\n")
+    print("| kernel | VALU | SALU | LDS | wait | VALU floor ms |")
+    print("|---|---|---|---|---|---|")
+    seen = set()
+    for (k, _), d in acc.items():
+        if k in seen or "SQ_INSTS_VALU" not in d or not k.startswith("k_"):
+            continue
+        seen.add(k)
+        v, sa, lds = d["SQ_INSTS_VALU"] / chunks, d.get("SQ_INSTS_SALU", 0) / chunks, d.get("SQ_INSTS_LDS", 0) / chunks
+        wait = d.get("SQ_WAIT_ANY", 0) / max(d.get("SQ_WAVE_CYCLES", 1), 1)
+        floor_ms = d["SQ_INSTS_VALU"] * 4 / 1024 / 2.4e9 * 1e3
+        print(f"| {k} | {v:.0f} | {sa:.0f} | {lds:.0f} | {wait:.0%} | {floor_ms:.3f} |")
 
 
 def traffic_summary(fetch_csv, write_csv, bench_json):
@@ -771,8 +802,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="values (default: the 2 GiB workload)")
-    ap.add_argument("--workload", choices=("sensor_f64", "mixed_f32"), default="sensor_f64",
-                    help="the workload of the timed steps (default: the 2 GiB float64 sensor series)")
+    ap.add_argument("--workload", choices=("sensor_f64", "mixed_f32", "decimal_f64"), default="sensor_f64",
+                    help="the workload of the timed steps (default: the 2 GiB float64 sensor series; "
+                         "decimal_f64: the sensor signal at 6 significant digits, no outliers, 2 GiB)")
     ap.add_argument("--form", choices=("two_pass", "single_pass"), default="two_pass",
                     help="compression form of the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -795,11 +827,17 @@ def main():
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="no GPU: summarise a rocprofv3 kernel trace (per-kernel durations) and exit")
     ap.add_argument("--skip", type=int, default=0, help="--trace-summary: dispatches per kernel to leave out")
+    ap.add_argument("--last", type=int, default=0, help="--trace-summary: keep only the last dispatches per kernel")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("COUNTER_CSV", "CHUNKS"),
+                    help="no GPU: instruction counters per chunk from a rocprofv3 SQ counter run, and exit")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="no GPU: HBM bytes per launch from two rocprofv3 counter runs, and exit")
     args = ap.parse_args()
     if args.trace_summary:
-        trace_summary(args.trace_summary, args.skip)
+        trace_summary(args.trace_summary, args.skip, args.last)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary[0], int(args.counter_summary[1]))
         return
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -823,7 +861,12 @@ def main():
     dev = torch.device("cuda", 0)
     f32 = args.workload == "mixed_f32"
     n = args.n or (1 << 29 if f32 else 1 << 28)
-    x = W.mixed_f32(n, seed=3) if f32 else W.sensor_f64(n, seed=2)
+    if f32:
+        x = W.mixed_f32(n, seed=3)
+    elif args.workload == "decimal_f64":
+        x = W.significant_f64(n, 5, 6)
+    else:
+        x = W.sensor_f64(n, seed=2)
     tdt = torch.float32 if f32 else torch.float64
     xd = torch.from_numpy(x).to(dev)
     nbytes = x.nbytes
@@ -890,9 +933,11 @@ def main():
     amax, bmax = (10, 6) if f32 else (22, 15)
     case1 = float(((a_bytes <= amax) & (b_bytes <= bmax)).float().mean().item())
 
-    workload = WORKLOAD if not f32 else ("mixed_f32: 536,870,912 float32 values (2 GiB): half sinusoid + "
-                                         "N(0, 0.01^2) noise at 0-4 decimal places, half 512^3 interpolated "
-                                         "fields at full precision")
+    workload = {"sensor_f64": WORKLOAD,
+                "mixed_f32": "mixed_f32: 536,870,912 float32 values (2 GiB): half sinusoid + N(0, 0.01^2) noise at "
+                             "0-4 decimal places, half 512^3 interpolated fields at full precision",
+                "decimal_f64": f"decimal_f64: {n:,} float64 values, the sensor signal rounded to 6 significant "
+                               "digits (Case 1 chunks)"}[args.workload]
     out = {
         "metric": METRIC,
         "value": round(nbytes / step_s / 1e9, 3),

@@ -143,8 +143,12 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
 //  2. Otherwise let L* = min(AMAX, BMAX-1-FL10(v_max)) <= every lim_i, the
 //     largest scale at which beta_hat stays within BMAX.  If every value
 //     passes the stopping test at L*, alpha_max is the least scale in
-//     [0, L*] at which all pass, found by bisection, and the recover check
-//     is applied there once.
+//     [0, L*] at which all pass.  A sample gives it in one chunk-wide round
+//     when the chunk's places are alike: each lane finds the place of its
+//     first value, and if every value passes at the largest of these, that
+//     is alpha_max (the recover check is applied in the same round).
+//     Otherwise a bisection over the remaining scales finds it, and the
+//     recover check is applied there once.
 //  3. A value failing at L* is an exception if L* is its own limit, or if it
 //     fails the full test at its own limit.
 //  4. If no failing value is an exception, alpha_max lies in (L*, max lim_i]
@@ -194,7 +198,49 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
     }
   }
   if (ballot(fail != 0) == 0) {
+    // alpha_max = max alpha_i lies in [0, L*].  First a sample: each lane
+    // finds the decimal place of its own first value by bisection over
+    // [0, L*] (per-lane bounds, the same number of rounds for all), and the
+    // chunk is tested once at the sample's largest place a_s.  If every
+    // value passes there, alpha_max = a_s exactly (the sampled value with
+    // place a_s fails at a_s - 1); otherwise alpha_max > a_s.  The bisection
+    // below then runs over what is left, usually nothing.
     int lo = 0, hi = lstar;
+    bool rec_bad = false;  // recover check at a_s (valid when every value passes there)
+    {
+      int slo = 0, shi = lstar;
+      for (int k = 0; (1 << k) < lstar + 1; ++k) {
+        const int mid = (slo + shi) >> 1;
+        F r;
+        if (eps_test<T>(vb[0], T::pow10(sm, mid), r)) shi = mid;
+        else slo = mid + 1;
+      }
+      const int as = (int)uniform((uint32_t)wave_max_i32(shi));
+      const F P = T::pow10(sm, as);
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < 17; ++k) {
+        F r;
+        const bool pass = eps_test<T>(vb[k], P, r);
+        bad |= !pass;
+        rec_bad |= pass && !recovers<T>(vb[k], r, P);
+      }
+      if (ballot(bad)) {
+        lo = as + 1;
+      } else {
+        // alpha_max = a_s, and its recover check is done
+        if (ballot(rec_bad)) {
+          A = T::AMAX + 1;
+          B = T::BMAX + 1;
+          case1 = false;
+          return;
+        }
+        A = as;
+        B = as + maxfl + 1;
+        case1 = true;
+        return;
+      }
+    }
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       const F P = T::pow10(sm, mid);
