@@ -170,11 +170,11 @@ def oracle_small_case(threads=None):
 
 def host_pipeline(codec, x, torch, reps=2):
     """Host -> host through the stream pipeline (Alg. 1): the default
-    geometry (4 streams, 1024-chunk batches) from pinned and from pageable
+    geometry (4 streams, 2048-chunk batches) from pinned and from pageable
     host buffers, and the paper's setting (16 streams, 4096 chunks) from
     pinned buffers; best of reps, GB/s of original bytes."""
     res = {}
-    for label, ns, bc, pinned in (("pinned", 4, 1024, True), ("pageable", 4, 1024, False),
+    for label, ns, bc, pinned in (("pinned", 4, 2048, True), ("pageable", 4, 2048, False),
                                   ("pinned_16x4096", 16, 4096, True)):
         codec.set_pipeline(ns, bc)
         xh = torch.from_numpy(x)
@@ -760,7 +760,7 @@ def sweeps(codec, torch, x):
             tc, td = min(tc, t1 - t0), min(td, t2 - t1)
         return round(x.nbytes / tc / 1e9, 2), round(x.nbytes / td / 1e9, 2)
     for ns in (1, 2, 4, 8, 16):
-        for bc in (256, 1024, 4096):
+        for bc in (256, 1024, 2048, 4096):
             codec.set_pipeline(ns, bc)
             c, d = host_rates()
             res["pipeline"][f"{ns}x{bc}"] = {"compress_gbps": c, "decompress_gbps": d}
@@ -768,7 +768,7 @@ def sweeps(codec, torch, x):
     for kind in ("event", "sync", "prealloc"):
         codec.set_scheduler(kind)
         for ns in (1, 2, 4, 8, 16, 32):
-            codec.set_pipeline(ns, 1024)
+            codec.set_pipeline(ns, 2048)
             res["schedulers"][f"{kind}_{ns}"] = host_rates()[0]
     codec.set_scheduler("event")
     codec.set_pipeline()

@@ -252,9 +252,9 @@ falcon_status falcon_decompress_host(falcon_ctx* ctx, const void* h_in, size_t i
 
 /* Sets the pipeline geometry used by the two calls above: n_streams HIP
  * streams (1..64; N_s of Alg. 1) and batch_chunks chunks of 1025 values per
- * batch (1..2^20).  Defaults: 4 streams, 1024 chunks (measured fastest on
+ * batch (1..2^20).  Defaults: 4 streams, 2048 chunks (measured fastest on
  * MI355X; the paper's Sec. 5.1.4 setting is 16 streams, 4096 chunks).
- * Device and pinned buffers (about 2 x 8.4 MB per stream at the default
+ * Device and pinned buffers (about 2 x 16.8 MB per stream at the default
  * batch, twice that when pageable buffers are staged) are allocated on
  * first use and kept until the geometry changes or the context is
  * destroyed.  FALCON_ERR_INVALID_ARG outside the ranges. */

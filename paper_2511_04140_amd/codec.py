@@ -352,7 +352,7 @@ class Codec:
         return out[: nout.value]
 
     # -- host -> host through the stream pipeline ---------------------------
-    def set_pipeline(self, n_streams: int = 4, batch_chunks: int = 1024):
+    def set_pipeline(self, n_streams: int = 4, batch_chunks: int = 2048):
         """Pipeline geometry: N_s streams, batch_chunks chunks per batch."""
         st = lib().falcon_set_pipeline(self._ctx, n_streams, batch_chunks)
         if st != 0:

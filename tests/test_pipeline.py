@@ -52,7 +52,7 @@ def _inputs():
     ]
 
 
-@pytest.mark.parametrize("streams,batch", [(1, 4096), (3, 1), (4, 3), (4, 1024), (16, 2), (16, 4096)])
+@pytest.mark.parametrize("streams,batch", [(1, 4096), (3, 1), (4, 3), (4, 1024), (4, 2048), (16, 2), (16, 4096)])
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
 @pytest.mark.parametrize("sched", ["event", "sync", "prealloc"])
 def test_pipeline_matches_oracle_and_device(codec, orc, streams, batch, pinned, sched):
@@ -124,7 +124,7 @@ def test_pipeline_rejects_corrupt_streams(codec, orc):
 @pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
 def test_pipeline_full_size_sensor_f64(codec, pinned):
     """The 2 GiB float64 workload host -> host with the default geometry
-    (4 streams, 1024-chunk batches): the stream of every scheduler equals the
+    (4 streams, 2048-chunk batches): the stream of every scheduler equals the
     device-resident one and decompresses to the input."""
     from paper_2511_04140_amd import workloads as W
     codec.set_pipeline()
