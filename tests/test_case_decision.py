@@ -1,8 +1,10 @@
 """The GPU decides a chunk's case (Eq. 3) without running Alg. 2 value by
 value: it applies the stopping test to every value once at the chunk's
-largest admissible scale L* = min(AMAX, BMAX - 1 - FL10(v_max)), bisects
-alpha_max below it with the stopping test, applies the recover check once
-at the result, and checks a value failing at L* at its own limit lim_i.  If
+largest admissible scale L* = min(AMAX, BMAX - 1 - FL10(v_max)); if all
+pass, it bisects the decimal places of a sample (the first value of each
+lane) and tests the whole chunk at the largest of them, which is alpha_max
+when every value passes there, else bisects alpha_max between it and L*
+with the stopping test; it applies the recover check once at the result, and checks a value failing at L* at its own limit lim_i.  If
 no failing value is an exception, it bisects alpha_max above L* with every
 value tested at min(a, lim_i), and applies the recover check once there (see
 decide_case in codec_kernels.hpp).  A value that is not an exception passes
@@ -78,6 +80,28 @@ def fast_decide(spec, v, stats=None):
     fail = ~ok_l
     if not fail.any():
         a, h = 0, lstar
+        # sample: the values each lane loads first (positions 1..64, clamped
+        # to the chunk); the largest of their least passing places bounds
+        # alpha_max from below, and it is alpha_max when every value passes
+        # there
+        samp = v[np.minimum(1 + np.arange(64), v.size - 1)]
+        slo, shi = np.zeros(64, np.int64), np.full(64, lstar, np.int64)
+        k = 0
+        while (1 << k) < lstar + 1:
+            mid = (slo + shi) >> 1
+            ok = np.array([spec.eps(samp[i:i + 1], spec.P[int(mid[i])])[0][0] for i in range(64)])
+            shi = np.where(ok, mid, shi)
+            slo = np.where(ok, slo, mid + 1)
+            k += 1
+        a_s = int(shi.max())
+        ok_s, _ = spec.eps(v, spec.P[a_s])
+        if ok_s.all():
+            if stats is not None:
+                stats["sample"] += 1
+            if not spec.full(v, spec.P[a_s]).all():
+                return spec.A + 1, spec.B + 1
+            return a_s, a_s + maxfl + 1
+        a = a_s + 1
         while a < h:
             mid = (a + h) // 2
             ok, _ = spec.eps(v, spec.P[mid])
@@ -183,7 +207,7 @@ def test_fast_decision_matches_literal_alg2(orc, dt, count):
     spec = Spec(dt)
     rng = np.random.default_rng(20251105 + (dt == np.float32))
     mismatches = []
-    stats = {"above": 0}
+    stats = {"above": 0, "sample": 0}
     for ch in _chunks(dt, rng, count):
         with np.errstate(all="ignore"):
             got = fast_decide(spec, ch, stats)
@@ -192,6 +216,7 @@ def test_fast_decision_matches_literal_alg2(orc, dt, count):
             mismatches.append((ch[:4], got, (A, B)))
     assert not mismatches, mismatches[:5]
     assert stats["above"] > count // 20
+    assert stats["sample"] > count // 10
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
