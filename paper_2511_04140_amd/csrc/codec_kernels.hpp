@@ -148,7 +148,9 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
 //     first value, and if every value passes at the largest of these, that
 //     is alpha_max (the recover check is applied in the same round).
 //     Otherwise a bisection over the remaining scales finds it, and the
-//     recover check is applied there once.
+//     recover check is applied there once.  When the wave's previous chunk
+//     was settled by the sample, the sample is tried before the test at L*,
+//     which a chunk it settles then skips.
 //  3. A value failing at L* is an exception if L* is its own limit, or if it
 //     fails the full test at its own limit.
 //  4. If no failing value is an exception, alpha_max lies in (L*, max lim_i]
@@ -158,9 +160,9 @@ __device__ __forceinline__ bool alg2_literal(const LdsTables& sm, const typename
 // When no value is an exception both bisections are exact and the recover
 // checks pass; so a failed recover check means some value is one, and the
 // chunk gets the exception header, as Alg. 2 would give it.
-template <class T>
+template <class T, bool HINT = true>
 __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename T::U (&vb)[17], int& A, int& B,
-                            bool& case1) {
+                            bool& case1, bool& hint) {
   using U = typename T::U;
   using F = typename T::F;
   const U mag_lo = T::u(T::pow10(sm, -T::AMAX));
@@ -188,59 +190,79 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
   }
   const int maxfl = (int)uniform((uint32_t)fl10<T>(sm, vmax));
   const int lstar = min(T::AMAX, T::BMAX - 1 - maxfl);
+  // The sample: each lane finds the decimal place of its own first value
+  // by bisection over [0, L*] (per-lane bounds, the same number of rounds
+  // for all), and the chunk is tested once, stopping test and recover
+  // check, at the sample's largest place a_s.  A value that passes both
+  // tests at a scale up to its limit is not an exception, and its place is
+  // at most that scale; so if every value passes at a_s, no value is an
+  // exception and alpha_max = a_s (the sampled value with place a_s fails
+  // at a_s - 1).
+  int as = 0;
+  bool s_bad = false, s_rec_bad = false;
+  auto sample = [&]() {
+    int slo = 0, shi = lstar;
+    for (int k = 0; (1 << k) < lstar + 1; ++k) {
+      const int mid = (slo + shi) >> 1;
+      F r;
+      if (eps_test<T>(vb[0], T::pow10(sm, mid), r)) shi = mid;
+      else slo = mid + 1;
+    }
+    as = (int)uniform((uint32_t)wave_max_i32(shi));
+    const F P = T::pow10(sm, as);
+    bool bad = false, rec_bad = false;
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+      F r;
+      const bool pass = eps_test<T>(vb[k], P, r);
+      bad |= !pass;
+      rec_bad |= pass && !recovers<T>(vb[k], r, P);
+    }
+    s_bad = ballot(bad) != 0;
+    s_rec_bad = ballot(rec_bad) != 0;
+  };
+  // The test at L*: fail gets the values of this lane that fail it.
   uint32_t fail = 0;
-  {
+  auto all_pass_at_lstar = [&]() {
     const F P = T::pow10(sm, lstar);
+    fail = 0;
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
       F r;
       set_bit(fail, !eps_test<T>(vb[k], P, r), k);
     }
-  }
-  if (ballot(fail != 0) == 0) {
-    // alpha_max = max alpha_i lies in [0, L*].  First a sample: each lane
-    // finds the decimal place of its own first value by bisection over
-    // [0, L*] (per-lane bounds, the same number of rounds for all), and the
-    // chunk is tested once at the sample's largest place a_s.  If every
-    // value passes there, alpha_max = a_s exactly (the sampled value with
-    // place a_s fails at a_s - 1); otherwise alpha_max > a_s.  The bisection
-    // below then runs over what is left, usually nothing.
-    int lo = 0, hi = lstar;
-    bool rec_bad = false;  // recover check at a_s (valid when every value passes there)
-    {
-      int slo = 0, shi = lstar;
-      for (int k = 0; (1 << k) < lstar + 1; ++k) {
-        const int mid = (slo + shi) >> 1;
-        F r;
-        if (eps_test<T>(vb[0], T::pow10(sm, mid), r)) shi = mid;
-        else slo = mid + 1;
-      }
-      const int as = (int)uniform((uint32_t)wave_max_i32(shi));
-      const F P = T::pow10(sm, as);
-      bool bad = false;
-#pragma unroll
-      for (int k = 0; k < 17; ++k) {
-        F r;
-        const bool pass = eps_test<T>(vb[k], P, r);
-        bad |= !pass;
-        rec_bad |= pass && !recovers<T>(vb[k], r, P);
-      }
-      if (ballot(bad)) {
-        lo = as + 1;
-      } else {
-        // alpha_max = a_s, and its recover check is done
-        if (ballot(rec_bad)) {
-          A = T::AMAX + 1;
-          B = T::BMAX + 1;
-          case1 = false;
-          return;
-        }
-        A = as;
-        B = as + maxfl + 1;
-        case1 = true;
-        return;
-      }
+    return ballot(fail != 0) == 0;
+  };
+  // With the hint set (the wave's previous chunk was settled by the sample)
+  // the sample comes first and, when every value passes there, settles the
+  // chunk without the test at L*.  Either order gives the same header.
+  bool all_pass = (HINT && hint) || all_pass_at_lstar();
+  if (all_pass) {
+    sample();
+    if (!s_bad && !s_rec_bad) {
+      A = as;
+      B = as + maxfl + 1;
+      case1 = true;
+      if (HINT) hint = true;
+      return;
     }
+    if (HINT && hint) {
+      hint = false;
+      all_pass = all_pass_at_lstar();
+    }
+  }
+  if (all_pass) {
+    // alpha_max = max alpha_i lies in [0, L*], at or above a_s.  If every
+    // value passes the stopping test at a_s, alpha_max = a_s and the failed
+    // recover check there means an exception; otherwise a bisection runs
+    // over what the sample leaves.
+    if (!s_bad) {
+      A = T::AMAX + 1;
+      B = T::BMAX + 1;
+      case1 = false;
+      return;
+    }
+    int lo = as + 1, hi = lstar;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       const F P = T::pow10(sm, mid);
@@ -566,10 +588,10 @@ __device__ __forceinline__ void compress_transform(const LdsTables& sm, uint8_t*
 // a2-a7: decimal places and case (Alg. 2, Alg. 3), then the transform.
 template <class T, bool TRANSPOSE = true, int V = kVarFalcon>
 __device__ __forceinline__ void compress_front(const LdsTables& sm, uint8_t* buf, const typename T::U (&vb)[17],
-                                               int lane, ChunkPlanes& cp) {
+                                               int lane, ChunkPlanes& cp, bool& hint) {
   bool case1;
   if constexpr (V == kVarElf) decide_case_elf<T>(sm, vb, cp.A, cp.B, case1);
-  else decide_case<T>(sm, vb, cp.A, cp.B, case1);
+  else decide_case<T>(sm, vb, cp.A, cp.B, case1, hint);
   compress_transform<T, TRANSPOSE>(sm, buf, vb, lane, case1, cp);
 }
 
@@ -589,8 +611,17 @@ struct ChunkStats {
 template <class T, int V = kVarFalcon>
 __device__ __forceinline__ ChunkStats chunk_stats_or(const ChunkPlanes& cp, int lane) {
   const uint32_t w = cp.w;
-  const uint64_t t0 = wave_transpose64(cp.or0, lane), t1 = wave_transpose64(cp.or1, lane);
-  const uint32_t nnz = (uint32_t)(__popcll(t0) + __popcll(t1));  // non-zero bytes of row `lane`
+  uint32_t nnz;  // non-zero bytes of row `lane`
+  if constexpr (T::W == 32) {
+    // 32 planes: both ORs fit one word, and one transpose hands lane p the
+    // bits of or0's plane p and lane 32 + p those of or1's
+    const uint64_t t = wave_transpose64(cp.or0 | (cp.or1 << 32), lane);
+    const uint32_t c = (uint32_t)__popcll(t);
+    nnz = c + xor_lane<32>(c, lane);
+  } else {
+    const uint64_t t0 = wave_transpose64(cp.or0, lane), t1 = wave_transpose64(cp.or1, lane);
+    nnz = (uint32_t)(__popcll(t0) + __popcll(t1));
+  }
   const bool row = (uint32_t)lane < w;
   const bool dense = row && (V == kVarDense || (V != kVarSparse && nnz >= 112));
   const uint32_t bytes = !row ? 0u : dense ? 128u : 16u + nnz;
@@ -1025,11 +1056,12 @@ __device__ __forceinline__ void empty_series_headers(const CompressArgs& a) {
 template <class T, int V, class Prefetch>
 __device__ __forceinline__ void size_chunk(const LdsTables& tab, uint8_t* buf, const CompressArgs& a,
                                            const CompressSeries& sd, uint64_t t, int lane,
-                                           typename T::U (&vb)[17], bool loaded, Prefetch&& prefetch) {
+                                           typename T::U (&vb)[17], bool loaded, bool& hint,
+                                           Prefetch&& prefetch) {
   const uint64_t c = t - sd.chunk0;
   if (!loaded) load_chunk<T>(sd, c, lane, vb);
   ChunkPlanes cp;
-  compress_front<T, false, V>(tab, buf, vb, lane, cp);
+  compress_front<T, false, V>(tab, buf, vb, lane, cp, hint);
   prefetch();
   const ChunkStats st = chunk_stats_or<T, V>(cp, lane);
   if (lane == 0) {
@@ -1104,6 +1136,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   if (t >= a.total_chunks) return;
   CompressSeries sd = find_series(a.one, a.many, a.nseries, t + a.t0);
   load_chunk<T>(sd, t + a.t0 - sd.chunk0, lane, vb);
+  bool hint = false;  // case-decision order (decide_case), carried across the wave's chunks
   for (;;) {
     const uint64_t tg = t + a.t0;
     const CompressSeries cur = sd;
@@ -1115,7 +1148,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         load_chunk<T>(sd, tn + a.t0 - sd.chunk0, lane, vb);
       }
     };
-    if (PASS == 1) size_chunk<T, V>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
+    if (PASS == 1) size_chunk<T, V>(sm.tab, buf, a, cur, tg, lane, vb, true, hint, prefetch);
     else write_chunk<T>(sm.tab, buf, a, cur, tg, lane, vb, true, prefetch);
     if (!more) break;
     t = tn;
@@ -1130,17 +1163,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int lane = lane_id();
   const int wid = (int)uniform(threadIdx.x >> 6);  // wave-uniform: keeps the chunk loop scalar
   uint8_t* buf = wave_bytes(sm, wid);
+  bool hint = false;
   for (uint64_t t = (uint64_t)blockIdx.x * NW + wid; t < a.total_chunks; t += a.total_waves) {
     const uint64_t tg = t + a.t0;
     const CompressSeries sd = find_series(a.one, a.many, a.nseries, tg);
     auto none = []() {};
     if (uniform(sd.dtype) == 2) {
       uint64_t vb[17];
-      if (PASS == 1) size_chunk<TF64, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      if (PASS == 1) size_chunk<TF64, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, hint, none);
       else write_chunk<TF64>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     } else {
       uint32_t vb[17];
-      if (PASS == 1) size_chunk<TF32, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
+      if (PASS == 1) size_chunk<TF32, kVarFalcon>(sm.tab, buf, a, sd, tg, lane, vb, false, hint, none);
       else write_chunk<TF32>(sm.tab, buf, a, sd, tg, lane, vb, false, none);
     }
   }
@@ -1290,8 +1324,8 @@ __device__ __forceinline__ void queue_chunk(const LdsTables& tab, uint8_t* buf, 
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
   // a2-a6 and the row statistics (a8-a9)
   ChunkPlanes cp;
-  bool case1;
-  decide_case<T>(tab, vb, cp.A, cp.B, case1);
+  bool case1, no_hint = false;  // the queue's waves take chunks far apart: no order hint
+  decide_case<T, false>(tab, vb, cp.A, cp.B, case1, no_hint);
   typename T::U e[16];
   transform_front<T, true>(tab, buf, vb, lane, case1, cp, e);
   const ChunkStats st = chunk_stats_or<T>(cp, lane);

@@ -4,10 +4,13 @@ largest admissible scale L* = min(AMAX, BMAX - 1 - FL10(v_max)); if all
 pass, it bisects the decimal places of a sample (the first value of each
 lane) and tests the whole chunk at the largest of them, which is alpha_max
 when every value passes there, else bisects alpha_max between it and L*
-with the stopping test; it applies the recover check once at the result, and checks a value failing at L* at its own limit lim_i.  If
-no failing value is an exception, it bisects alpha_max above L* with every
-value tested at min(a, lim_i), and applies the recover check once there (see
-decide_case in codec_kernels.hpp).  A value that is not an exception passes
+with the stopping test (after a chunk the sample settled, the GPU tries
+the sample before the test at L*, which a chunk it settles then skips); it
+applies the recover check once at the result, and checks a value failing
+at L* at its own limit lim_i.  If no failing value is an exception, it
+bisects alpha_max above L* with every value tested at min(a, lim_i), and
+applies the recover check once there (see decide_case in
+codec_kernels.hpp).  A value that is not an exception passes
 both tests at every scale from its decimal place up to its limit (Thm. 2,
 Thm. 4), so the bisections are exact when no value is an exception, and a
 failed recover check at their result means some value is one.
@@ -63,9 +66,27 @@ class Spec:
         return ok & (self.bits(back) == self.bits(v))
 
 
-def fast_decide(spec, v, stats=None):
+def _sample(spec, v, lstar):
+    """The sample: the values each lane loads first (positions 1..64,
+    clamped to the chunk), each bisected for its least passing place over
+    [0, L*]; returns the largest of these places, a_s."""
+    samp = v[np.minimum(1 + np.arange(64), v.size - 1)]
+    slo, shi = np.zeros(64, np.int64), np.full(64, lstar, np.int64)
+    k = 0
+    while (1 << k) < lstar + 1:
+        mid = (slo + shi) >> 1
+        ok = np.array([spec.eps(samp[i:i + 1], spec.P[int(mid[i])])[0][0] for i in range(64)])
+        shi = np.where(ok, mid, shi)
+        slo = np.where(ok, slo, mid + 1)
+        k += 1
+    return int(shi.max())
+
+
+def fast_decide(spec, v, stats=None, sample_first=False):
     """Returns (A, B); stats counts the chunks settled by the bisection
-    above L*."""
+    above L* and by the sample.  With sample_first the sample is tried
+    before the test at L* (the order the GPU takes after a chunk the sample
+    settled); both orders must give the same header."""
     b = spec.bits(v)
     m = spec.mag(b)
     lo, hi = spec.bits(spec.P[-spec.A])[()], spec.bits(spec.P[spec.B])[()]
@@ -76,24 +97,20 @@ def fast_decide(spec, v, stats=None):
         return 0, 0
     maxfl = int(spec.fl10(np.array([vmax], spec.U))[0])
     lstar = min(spec.A, spec.B - 1 - maxfl)
+    if sample_first:
+        # every value passes both tests at a_s: no exception, alpha_max = a_s
+        a_s = _sample(spec, v, lstar)
+        if spec.full(v, spec.P[a_s]).all():
+            if stats is not None:
+                stats["first"] += 1
+            return a_s, a_s + maxfl + 1
     ok_l, _ = spec.eps(v, spec.P[lstar])
     fail = ~ok_l
     if not fail.any():
         a, h = 0, lstar
-        # sample: the values each lane loads first (positions 1..64, clamped
-        # to the chunk); the largest of their least passing places bounds
-        # alpha_max from below, and it is alpha_max when every value passes
-        # there
-        samp = v[np.minimum(1 + np.arange(64), v.size - 1)]
-        slo, shi = np.zeros(64, np.int64), np.full(64, lstar, np.int64)
-        k = 0
-        while (1 << k) < lstar + 1:
-            mid = (slo + shi) >> 1
-            ok = np.array([spec.eps(samp[i:i + 1], spec.P[int(mid[i])])[0][0] for i in range(64)])
-            shi = np.where(ok, mid, shi)
-            slo = np.where(ok, slo, mid + 1)
-            k += 1
-        a_s = int(shi.max())
+        # the largest place of the sample bounds alpha_max from below, and it
+        # is alpha_max when every value passes there
+        a_s = _sample(spec, v, lstar)
         ok_s, _ = spec.eps(v, spec.P[a_s])
         if ok_s.all():
             if stats is not None:
@@ -207,16 +224,18 @@ def test_fast_decision_matches_literal_alg2(orc, dt, count):
     spec = Spec(dt)
     rng = np.random.default_rng(20251105 + (dt == np.float32))
     mismatches = []
-    stats = {"above": 0, "sample": 0}
+    stats = {"above": 0, "sample": 0, "first": 0}
     for ch in _chunks(dt, rng, count):
-        with np.errstate(all="ignore"):
-            got = fast_decide(spec, ch, stats)
         A, B, w, _ = orc.chunk_info(ch)
-        if got != (A, B):
-            mismatches.append((ch[:4], got, (A, B)))
+        for first in (False, True):
+            with np.errstate(all="ignore"):
+                got = fast_decide(spec, ch, stats, sample_first=first)
+            if got != (A, B):
+                mismatches.append((ch[:4], first, got, (A, B)))
     assert not mismatches, mismatches[:5]
-    assert stats["above"] > count // 20
+    assert stats["above"] > count // 10
     assert stats["sample"] > count // 10
+    assert stats["first"] > count // 10
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
