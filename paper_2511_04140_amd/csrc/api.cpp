@@ -154,7 +154,7 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
     a.meta = l.meta;
     a.gsizes = l.gsizes;
     a.offsets = l.offsets;
-    const int nw = variant ? kVariantWaves : kCompressWaves;
+    const int nw = variant ? kVariantWaves : compress_waves((int)dt);
     const int g1 = grid_for(variant ? ctx->grid_v[dt][variant][1] : max_grid_c(ctx, dt, 1, nw), nc, nw);
     const int g2 = grid_for(variant ? ctx->grid_v[dt][variant][2] : max_grid_c(ctx, dt, 2, nw), nc, nw);
     auto launch = [&](int pass, int grid) {

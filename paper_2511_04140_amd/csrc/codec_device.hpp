@@ -189,6 +189,18 @@ struct TF32 {
   static __device__ __forceinline__ F pow10(const LdsTables& s, int k) { return s.p32[k + POFF]; }
 };
 
+// Per-wave LDS buffer of a one-dtype decoder, in 16-byte blocks: a chunk's
+// values in their skewed slots, which also holds that dtype's largest
+// payload at any byte phase (with the clamped row reads past it).  The
+// float32 decoder thus takes half the LDS of the float64 one, and its
+// registers, not its LDS, set its occupancy.
+template <class T>
+constexpr int wave_blocks() {
+  return (kGSlots * (int)sizeof(typename T::U) + 15) / 16;
+}
+static_assert(wave_blocks<TF64>() * 16 == kWaveLds, "float64 buffer");
+static_assert(wave_blocks<TF32>() * 16 >= 15 + TF32::BOUND + 145, "float32 payloads fit");
+
 // Zigzag of Eq. 4: (x << 1) xor (x >> (W-1)), arithmetic shift.
 template <class U>
 __device__ __forceinline__ U zigzag(U x) {

@@ -877,7 +877,7 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   for (int i = 0; i < 16; ++i) lo[i] = hi[i] = 0;
   uint32_t cur = uniform(pad + 3 + T::ZB + nflag);
   bool ubad = uniform((uint32_t)bad) != 0;
-  constexpr uint32_t kLim = kWaveLds - 1;
+  constexpr uint32_t kLim = wave_blocks<T>() * 16 - 1;
   static_assert(15 + T::BOUND + 144 <= kLim, "clamped row reads of a valid chunk are never moved");
   const uint32_t sh = 6u - 2u * ((uint32_t)lane & 3u);  // bitmap bit of row byte 2L + 1
   // a dense row's bytes for this lane sit at 2L and 2L + 1 past the cursor;
@@ -1121,9 +1121,13 @@ __device__ __forceinline__ void pass_prologue(BlockLdsT<NW, WB>& sm, const Compr
 // PASS 1 = size pass, 2 = write pass; one dtype per launch.  V selects an
 // ablation variant (size pass only: the write pass follows the flags the
 // size pass stored); WB is the per-wave LDS buffer in 16-byte blocks, which
-// an all-sparse float64 chunk (up to 9235 bytes) needs larger.
-template <class T, int NW, int PASS, int V = kVarFalcon, int WB = kWaveLds / 16>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_compress_pass(CompressArgs a) {
+// an all-sparse float64 chunk (up to 9235 bytes) needs larger.  With the
+// float32 buffer of wave_blocks, the float32 passes hold their registers to
+// 80 and run 6 waves per SIMD; the float64 ones are held to 4 by LDS.
+template <class T, int NW, int PASS, int V = kVarFalcon, int WB = wave_blocks<T>()>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu((T::W == 32 && WB == wave_blocks<T>()) ? 6 : 4))) void k_compress_pass(
+    CompressArgs a) {
   __shared__ BlockLdsT<NW, WB> sm;
   pass_prologue(sm, a, PASS == 2);
   const int lane = lane_id();
@@ -1490,9 +1494,12 @@ __device__ __forceinline__ void decompress_loop(const DecompressArgs& a, uint8_t
   }
 }
 
+// The float32 decoder's LDS buffer (wave_blocks) and registers (at most 80
+// with 6 waves per SIMD) let it hold 6 waves per SIMD; the float64 one is
+// held to 4 by its LDS buffer.
 template <class T>
-__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(4))) void k_decompress(DecompressArgs a) {
-  __shared__ BlockLdsT<kWavesD> sm;
+__global__ __launch_bounds__(64 * kWavesD) __attribute__((amdgpu_waves_per_eu(T::W == 32 ? 6 : 4))) void k_decompress(DecompressArgs a) {
+  __shared__ BlockLdsT<kWavesD, wave_blocks<T>()> sm;
   load_tables(sm.tab);
   __syncthreads();
   const int lane = lane_id();

@@ -92,6 +92,11 @@ struct DecompressArgs {
 };
 
 constexpr int kCompressWaves = 16;    // default wavefronts per compression workgroup
+// The float32 passes run 6 waves per SIMD (their LDS buffer is half the
+// float64 one and their registers are held to 80), which workgroups of 8
+// waves fill (3 per CU); 16-wave workgroups would fit only one.
+constexpr int kCompressWaves32 = 8;
+constexpr int compress_waves(int dtype) { return dtype == 1 ? kCompressWaves32 : kCompressWaves; }
 constexpr int kDecompressWaves = 4;   // wavefronts per decompression workgroup
 
 // Kernel forms: one instantiation per dtype (1 = f32, 2 = f64) and a mixed

@@ -59,15 +59,16 @@ falcon_status setup(int dev, DeviceState** out) {
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FALCON_ERR_DEVICE;
     d.ptr = static_cast<uint8_t*>(p);
     for (int form = 1; form <= 2; ++form)
-      for (int pass = 1; pass <= 2; ++pass) d.grid[form][pass] = max_grid_compress(dev, form, pass, kCompressWaves);
+      for (int pass = 1; pass <= 2; ++pass)
+        d.grid[form][pass] = max_grid_compress(dev, form, pass, compress_waves(form));
     d.ready = true;
   }
   *out = &d;
   return FALCON_OK;
 }
 
-int grid_of(int max_grid, uint64_t nchunks) {
-  uint64_t want = (nchunks + kCompressWaves - 1) / kCompressWaves;
+int grid_of(int max_grid, uint64_t nchunks, int nw) {
+  uint64_t want = (nchunks + nw - 1) / nw;
   if (want < 1) want = 1;
   return (int)(want < (uint64_t)max_grid ? want : (uint64_t)max_grid);
 }
@@ -126,15 +127,16 @@ extern "C" falcon_status falcon_compress_noalloc(const void* d_in, size_t n, fal
   // meta and sizes, the scan the tile sums and offsets; the control block
   // takes an error word only for a chunk size outside [0, 2^32), which never
   // happens, so nothing needs clearing between calls
-  const int g1 = grid_of(d->grid[dt][1], nc), g2 = grid_of(d->grid[dt][2], nc);
+  const int nw = compress_waves((int)dt);
+  const int g1 = grid_of(d->grid[dt][1], nc, nw), g2 = grid_of(d->grid[dt][2], nc, nw);
   if (nc) {
-    a.total_waves = (uint32_t)(g1 * kCompressWaves);
-    if ((st = dev_err(launch_compress(a, (int)dt, 1, kCompressWaves, g1, s))) != FALCON_OK) return st;
+    a.total_waves = (uint32_t)(g1 * nw);
+    if ((st = dev_err(launch_compress(a, (int)dt, 1, nw, g1, s))) != FALCON_OK) return st;
     if ((st = dev_err(launch_scan_sizes(sizes, nc, 0, ~0u, ~0ull, tiles, offsets, ctl, 1, s))) != FALCON_OK)
       return st;
   }
-  a.total_waves = (uint32_t)(g2 * kCompressWaves);
-  if ((st = dev_err(launch_compress(a, (int)dt, 2, kCompressWaves, g2, s))) != FALCON_OK) return st;
+  a.total_waves = (uint32_t)(g2 * nw);
+  if ((st = dev_err(launch_compress(a, (int)dt, 2, nw, g2, s))) != FALCON_OK) return st;
   // an empty input has no chunk to write its length
   if (n == 0 && d_out_len)
     return dev_err(launch_fill_u64(reinterpret_cast<uint64_t*>(d_out_len), 1, 32, s));
