@@ -1086,9 +1086,16 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   const uint64_t c = t - sd.chunk0;
   const uint64_t nc = (sd.n + kChunk - 1) / kChunk;
   if (!loaded) load_chunk<T>(sd, c, lane, vb);
-  const const_ptr<uint64_t> mp = cst(reinterpret_cast<const uint64_t*>(a.meta + t));
+  // The chunk's metadata and offset come through scalar loads at a
+  // wave-uniform index (readfirstlane): a vector load would count against
+  // the vector-memory counter, and waiting for it would also wait for the
+  // next chunk's prefetch and this wave's outstanding stores.
+  const uint64_t tu = uniform64(t);
+  const const_ptr<uint64_t> mp = cst(reinterpret_cast<const uint64_t*>(a.meta + tu));
   const uint64_t flags = uniform64(mp[0]);
   const uint64_t m1 = uniform64(mp[1]);
+  const uint64_t base = a.relative ? uniform64(cst(a.offsets)[uniform64(sd.chunk0)]) : 0;
+  const uint64_t off = uniform64(cst(a.offsets)[tu]) - base;
   const uint32_t S = (uint32_t)m1;
   ChunkPlanes cp;
   cp.A = (int)((m1 >> 32) & 0xFF);
@@ -1097,8 +1104,6 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   prefetch();
   // the payload goes to dst; it is assembled at dst's 16-byte phase so that
   // the copy moves whole aligned blocks
-  const uint64_t base = a.relative ? uniform64(cst(a.offsets)[sd.chunk0]) : 0;
-  const uint64_t off = uniform64(cst(a.offsets)[t]) - base;
   uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
   assemble_payload<T>(buf + ph, cp, flags, S, lane);
