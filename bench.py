@@ -616,11 +616,11 @@ def studies(codec, torch):
 
 def _kernel_short(name):
     """Short label of a kernel name as rocprofv3 prints it."""
-    for key, label in (("k_compress_pass<falcon_dev::TF64, 16, 1", "k_compress_pass<size>"),
-                       ("k_compress_pass<falcon_dev::TF64, 16, 2", "k_compress_pass<write>"),
-                       ("k_compress_pass<falcon_dev::TF32, 16, 1", "k_compress_pass<size>"),
-                       ("k_compress_pass<falcon_dev::TF32, 16, 2", "k_compress_pass<write>"),
-                       ("k_compress_queue<", "k_compress_queue"), ("k_compress_pass_mixed<", "k_compress_pass_mixed"),
+    import re
+    m = re.search(r"k_compress_pass<falcon_dev::TF(?:64|32), \d+, ([12]), 0,", name)
+    if m:
+        return "k_compress_pass<size>" if m.group(1) == "1" else "k_compress_pass<write>"
+    for key, label in (("k_compress_queue<", "k_compress_queue"), ("k_compress_pass_mixed<", "k_compress_pass_mixed"),
                        ("k_decompress_mixed", "k_decompress_mixed"), ("k_decompress<", "k_decompress"),
                        ("k_scan_tiles", "k_scan_tiles"), ("k_scan_tile_sums", "k_scan_tile_sums"),
                        ("k_scan_apply", "k_scan_apply"), ("k_fill_u64", "k_fill_u64"),
