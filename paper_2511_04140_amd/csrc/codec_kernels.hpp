@@ -221,15 +221,32 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
     s_bad = ballot(bad) != 0;
     s_rec_bad = ballot(rec_bad) != 0;
   };
-  // The test at L*: fail gets the values of this lane that fail it.
+  // The test at L*: fail gets the values of this lane that fail it.  A
+  // failing value whose own limit min(AMAX, BMAX - 1 - FL10(|v|)) equals L*
+  // is an exception (step 3); its limit is L* exactly when L* = AMAX or
+  // FL10(|v|) = FL10(v_max), i.e. |v| >= fl(10^FL10(v_max)), one compare.
+  // The values are tested four slots at a time, and the test stops at the
+  // first such exception in the wave (quick): the chunk's header is then
+  // the exception header whatever the other values hold.
   uint32_t fail = 0;
+  bool quick = false;
+  const U thr = T::u(T::pow10(sm, maxfl));
   auto all_pass_at_lstar = [&]() {
     const F P = T::pow10(sm, lstar);
     fail = 0;
+    bool qe = false;
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
       F r;
-      set_bit(fail, !eps_test<T>(vb[k], P, r), k);
+      const bool f = !eps_test<T>(vb[k], P, r);
+      set_bit(fail, f, k);
+      qe |= f && (lstar == T::AMAX || T::mag(vb[k]) >= thr);
+      if ((k & 3) == 3 || k == 16) {
+        if (ballot(qe)) {
+          quick = true;
+          return false;
+        }
+      }
     }
     return ballot(fail != 0) == 0;
   };
@@ -293,19 +310,11 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
     return;
   }
   {
-    // A failing value whose own limit equals L* is an exception.  Its limit
-    // min(AMAX, BMAX - 1 - FL10(|v|)) equals L* exactly when L* = AMAX or
-    // FL10(|v|) = FL10(v_max), i.e. |v| >= fl(10^FL10(v_max)): one compare,
-    // tried for all failing values before any full test.
-    const U thr = T::u(T::pow10(sm, maxfl));
+    // Some value fails at L*.  Unless the test above already met an
+    // exception whose limit is L*, every failing value is checked in full
+    // at its own limit (above L*: its limit is not L*).
     bool e = false;
-    if (lstar == T::AMAX) {
-      e = fail != 0;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 17; ++k) e |= ((fail >> k) & 1u) && T::mag(vb[k]) >= thr;
-    }
-    if (!ballot(e)) {
+    if (!quick) {
 #pragma unroll
       for (int k = 0; k < 17; ++k) {
         if ((fail >> k) & 1u) {
@@ -315,7 +324,7 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
         }
       }
     }
-    if (ballot(e)) {
+    if (quick || ballot(e)) {
       A = T::AMAX + 1;
       B = T::BMAX + 1;
       case1 = false;
