@@ -136,6 +136,7 @@ struct TF64 {
   using U = uint64_t;
   using S = int64_t;
   static constexpr int W = 64, ZB = 8, AMAX = 22, BMAX = 15, MANT = 52;
+  static constexpr int MARKSTEIN_MAX = 21;  // decoder's division-free quotient up to 5^alpha < 2^51
   static constexpr int EXPMAX = 0x7FF, BIAS = 1023;
   // |v| >= 2^50 > 10^15 means FL10 >= 15 (beta > 15 at alpha = 0);
   // |v| < 2^-74 < fl(10^-22) means FL10 <= -23 (decimal place > 22).
@@ -166,6 +167,7 @@ struct TF32 {
   using U = uint32_t;
   using S = int32_t;
   static constexpr int W = 32, ZB = 4, AMAX = 10, BMAX = 6, MANT = 23;
+  static constexpr int MARKSTEIN_MAX = 10;  // decoder's division-free quotient (every alpha)
   static constexpr int EXPMAX = 0xFF, BIAS = 127;
   // |v| >= 2^20 > 10^6 means FL10 >= 6; |v| < 2^-34 < fl(10^-10) means
   // FL10 <= -11.

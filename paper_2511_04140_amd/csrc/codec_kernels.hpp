@@ -955,13 +955,30 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   wave_lds_sync();
   U* vals = reinterpret_cast<U*>(buf);
   if (case1) {
+    // Inverse Eq. 3: v = g / 10^alpha, correctly rounded.  With y the
+    // correctly rounded reciprocal of P = 10^alpha and q = RN(g * y), the
+    // residual g - q * P is exact (one fused multiply-add) and
+    // RN(q + (g - q * P) * y) is RN(g / P) (Markstein's correction step):
+    // q lies within 2 ulps of z = g / P, so q + (g - q P) y = z + (z - q)
+    // (P y - 1) is within 2^-52 ulp of z; and z, with |g| < 2^53, lies at
+    // least ulp(z) / (2 * 5^alpha) from every midpoint between two floats
+    // (never on one), which is more for 5^alpha < 2^51, i.e. alpha <= 21 in
+    // binary64 (binary32: checked over every |g| < 10^6 and alpha <= 10).
+    // alpha = 22 in binary64 keeps the IEEE division.
     const F P = T::pow10(sm, A);
+    const F y = (F)1 / P;
+    const bool markstein = A <= T::MARKSTEIN_MAX;  // wave-uniform
+    auto quot = [&](F g) {
+      if (!markstein) return g / P;
+      const F q = g * y;
+      return T::fma(T::fma(-q, P, g), y, q);
+    };
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const uint32_t idx = 16u * lane + 1 + i;
-      vals[idx + (idx >> 4)] = T::u((F)(S_)(U)(basev + gv[i]) / P);
+      vals[idx + (idx >> 4)] = T::u(quot((F)(S_)(U)(basev + gv[i])));
     }
-    if (lane == 0) vals[0] = T::u((F)(S_)z1 / P);
+    if (lane == 0) vals[0] = T::u(quot((F)(S_)z1));
   } else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {

@@ -93,6 +93,12 @@ for d in range(0, 16):
     SMALL_CASES.append((f"decimal{d}_f64",
                         lambda W, rng, d=d: W.decimal_f64(7 * 1025 + 100, seed=100 + d, places=d,
                                                           magnitude=10.0 ** (12 - min(d, 12)))))
+for d in range(16, 23):
+    # the largest decimal places of Case 1: the decoder's division-free
+    # quotient up to 21 places, the IEEE division at 22
+    SMALL_CASES.append((f"decimal{d}_f64",
+                        lambda W, rng, d=d: W.decimal_f64(7 * 1025 + 100, seed=100 + d, places=d,
+                                                          magnitude=10.0 ** (12 - d))))
 for d in (12, 14, 15, 16):
     # mixed magnitudes at high precision: chunks whose small values need more
     # places than L* allows (the bisection above L*)
@@ -102,6 +108,11 @@ for d in range(0, 8):
     SMALL_CASES.append((f"decimal{d}_f32",
                         lambda W, rng, d=d: W.decimal_f32(7 * 1025 + 100, seed=200 + d, places=d,
                                                           magnitude=10.0 ** (5 - min(d, 5)))))
+for d in (8, 9, 10):
+    # up to AMAX = 10 places in Case 1 (five significant digits)
+    SMALL_CASES.append((f"decimal{d}_f32",
+                        lambda W, rng, d=d: W.decimal_f32(7 * 1025 + 100, seed=200 + d, places=d,
+                                                          magnitude=10.0 ** (5 - d))))
 
 
 @pytest.mark.parametrize("name,make", SMALL_CASES, ids=[c[0] for c in SMALL_CASES])
