@@ -72,6 +72,20 @@ __device__ __forceinline__ bool recovers(typename T::U b, typename T::F r, typen
   return T::u(r / P) == b;
 }
 
+// The recover check for an integer r with |r| < 10^BMAX and y = RN(1/P):
+// RN(r / P) is RN(q + RN(r - q P) y) with q = RN(r y) up to alpha =
+// MARKSTEIN_MAX (see the decoder's inverse of Eq. 3, decompress_chunk), so
+// one product and two fused multiply-adds give the quotient to compare
+// with v; above that alpha, recovers().  alpha is wave-uniform.
+template <class T>
+__device__ __forceinline__ bool recovers_int(typename T::U b, typename T::F r, typename T::F P, typename T::F y,
+                                             int alpha) {
+  using F = typename T::F;
+  if (alpha > T::MARKSTEIN_MAX) return recovers<T>(b, r, P);
+  const F q = r * y;
+  return T::u(T::fma(T::fma(-q, P, r), y, q)) == b;
+}
+
 // Stopping test plus the recover check of Alg. 2: round(v (x) 10^a) / 10^a
 // must give back v bit for bit.
 template <class T>
@@ -210,13 +224,14 @@ __device__ __forceinline__ void decide_case(const LdsTables& sm, const typename 
     }
     as = (int)uniform((uint32_t)wave_max_i32(shi));
     const F P = T::pow10(sm, as);
+    const F y = (F)1 / P;
     bool bad = false, rec_bad = false;
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
       F r;
-      const bool pass = eps_test<T>(vb[k], P, r);
+      const bool pass = eps_test<T>(vb[k], P, r);  // |r| < 10^BMAX when it passes (as <= L*)
       bad |= !pass;
-      rec_bad |= pass && !recovers<T>(vb[k], r, P);
+      rec_bad |= pass && !recovers_int<T>(vb[k], r, P, y, as);
     }
     s_bad = ballot(bad) != 0;
     s_rec_bad = ballot(rec_bad) != 0;

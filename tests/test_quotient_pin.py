@@ -8,7 +8,9 @@ rounded fma: every binary32 case Case 1 can produce (|g| < 10^6, alpha
 <= 10), and for binary64 every |g| <= 2 * 10^6 plus 2 * 10^6 random g below
 10^15 at each alpha <= 21 (alpha = 22 keeps the division in the kernel).
 Without the correction step the same program finds millions of
-mismatches."""
+mismatches.  The compressor's recover check of Alg. 2 (recovers_int, used
+by the case decision's sample) computes the same quotient for integers
+r = round(v * 10^alpha) in the same ranges."""
 import os
 import subprocess
 
