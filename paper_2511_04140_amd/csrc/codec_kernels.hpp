@@ -1269,10 +1269,13 @@ __device__ __forceinline__ uint64_t status_word(uint64_t kind, uint32_t tag, uin
 
 // The next chunk of the calling wave (lane 0 takes the ticket; every lane
 // gets the chunk).  Counter g hands out chunks g, g + G, g + 2G, ... in
-// increasing order to the workgroups b = g mod G; one counter would
-// serialise every chunk on one memory location.
+// increasing order to the waves with (workgroup + wave index) mod G = g;
+// one counter would serialise every chunk on one memory location.  Mixing
+// the wave index in spreads each counter's waves over all XCDs (workgroups
+// are dealt to XCDs round-robin), so that no counter falls behind with a
+// slower XCD.
 __device__ __forceinline__ uint64_t take_ticket(const CompressArgs& a, int lane) {
-  const uint32_t g = blockIdx.x % a.qgroups;
+  const uint32_t g = (blockIdx.x + uniform(threadIdx.x >> 6)) % a.qgroups;
   uint64_t k = 0;
   if (lane == 0)
     k = __hip_atomic_fetch_add(a.qctr + (size_t)kQueueStride * g, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
