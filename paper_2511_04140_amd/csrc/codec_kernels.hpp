@@ -892,6 +892,9 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       flags = (flags << 8) | (uint32_t)__builtin_amdgcn_readlane((int)hb, 3 + T::ZB + (int)f);
   }
   flags = uniform64(flags);
+  // a row's scheme bit is tested in one 32-bit half of the flags: one
+  // scalar bit test
+  const uint32_t flo = (uint32_t)flags, fhi = (uint32_t)(flags >> 32);
   // d2: rows -> bit-plane fields of this lane (row bytes 2L, 2L+1).  The
   // row cursor and the error flag are wave-uniform; reads use clamped
   // addresses so that a corrupt stream never reads outside the buffer (its
@@ -914,12 +917,12 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
     constexpr int p = decltype(pc)::value;
     if (p < (int)w) {
       uint32_t fld;
-      const bool dense = (flags >> p) & 1;
+      const bool dense = ((p >= 32 ? fhi : flo) >> (p & 31)) & 1u;
       uint32_t nnz = 0;  // sparse rows: non-zero bytes after the bitmap
       // reads are kept inside the buffer by clamping the (scalar) cursor: in
       // a valid chunk every row ends by total <= 15 + BOUND, below both
-      // clamps, so they never move a read; a corrupt chunk is reported
-      // through ubad
+      // clamps, so they never move a read; a corrupt chunk is reported by
+      // the final cursor check
       if (dense) {
         // two byte reads (see l2p above)
         const uint32_t c0 = min(cur, kLim - 128);
@@ -935,10 +938,11 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
         const uint32_t r0 = d[0], r1 = d[nz0];
         fld = (nz0 ? r0 : 0u) | ((nz1 ? r1 : 0u) << 8);
       }
-      // the row's extent, checked and stepped over after the join so that
-      // the cursor stays one scalar value
+      // the row's extent, stepped over after the join so that the cursor
+      // stays one scalar value; the cursor only grows, so a row that runs
+      // past the payload leaves it above total, which the check after the
+      // last row reports
       const uint32_t row = dense ? 128u : 16u + nnz;
-      ubad |= cur + row > total;
       cur += row;
       plane_put<p>(lo, hi, fld);
     }
