@@ -31,13 +31,16 @@ WORKLOAD = ("sensor_f64: 268,435,456 float64 values (2 GiB) in 65,536-value segm
 
 
 def kernel_source_digest():
-    """Digest of the device code (every .hip source and the device headers)."""
+    """Digest of the device code (every .hip source and the device headers)
+    and of the build script that holds its compile flags."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_04140_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith(".hip") or name in ("codec_device.hpp", "codec_kernels.hpp"):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "paper_2511_04140_amd", "build.py"), "rb") as f:
+        h.update(b"build.py\0" + f.read())
     return h.hexdigest()[:16]
 
 

@@ -25,6 +25,15 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+# Per-source additions.  The float32 kernels are built with uniform branches
+# left unstructured: a wave-uniform if/else then compiles to one scalar
+# branch instead of exec-mask bookkeeping (per bit-plane row in the payload
+# assembly and the decoder).  Measured on MI355X: float32 compression 4.6 %
+# and decoding 2.6 % faster; the float64 kernels measured 1-2 % slower and
+# keep the default.
+SOURCE_FLAGS = {
+    "kernels_f32.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=1"],
+}
 
 
 def build(verbose: bool = False) -> str:
@@ -33,7 +42,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-        cmd = [hipcc, *FLAGS, "-c", "-x", "hip", src, "-o", obj]
+        cmd = [hipcc, *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), "-c", "-x", "hip", src, "-o", obj]
         if verbose:
             print(" ".join(cmd))
         r = subprocess.run(cmd, capture_output=True, text=True)
