@@ -79,7 +79,9 @@ struct PipeLane {
 // co-resident workgroups.
 struct BatchGeom {
   int split = 1;
-  int nw = falcon_dev::kCompressWaves;
+  // 8-wave workgroups by default: the float32 kernels then run 6 waves per
+  // SIMD (three workgroups per CU), the float64 ones 4, as with 16
+  int nw = falcon_dev::kCompressWaves32;
   int grid_pct = 100;
   int form = 0;  // compression: 0 two passes (static striding), 1 single pass (work queue, look-back)
 };
