@@ -1,7 +1,8 @@
 """GPU parity on whole streams: every byte of the HIP codec's stream against
 the CPU oracle, at the full sizes of the measured workloads, on every
 float32 bit pattern, on batch plans with more chunks than the device holds
-waves, and on the oracle's own edge chunks.
+waves, on the 10,000-series batch of the batched measurement, and on the
+oracle's own edge chunks.
 
 A full-size stream is compared slice by slice: the oracle compresses
 chunk-aligned slices of the input in threads (a chunk's encoding does not
@@ -260,3 +261,59 @@ def test_batch_plan_more_chunks_than_waves(codec, orc):
             assert torch.equal(y.view(torch.uint8), x.view(torch.uint8)), f"replay {rep}"
     plan.close()
     dplan.close()
+
+
+def test_batch_of_10000_series(codec, orc):
+    """The 10,000-series batch of the batched measurement (lengths
+    log-uniform on [1,024, 369,000] values, 60 % float64, 0-6 decimal places
+    per series, about 4 GB) through one tuned, graph-captured compression
+    plan and one decompression plan, writing into one device buffer each as
+    the measurement does: every series' stream equals the oracle's byte for
+    byte, and every series comes back bit for bit."""
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    xs = W.batch_series()
+    tdt = lambda x: torch.float64 if x.dtype == np.float64 else torch.float32
+    align = lambda v: (v + 255) // 256 * 256
+    in_off, out_off, bounds = [], [], []
+    ti = to = 0
+    for x in xs:
+        in_off.append(ti)
+        ti += align(x.nbytes)
+        bounds.append(C.compress_bound(x.size, tdt(x)))
+        out_off.append(to)
+        to += align(bounds[-1])
+    _log(f"[batch-10000] {len(xs)} series, {sum(x.nbytes for x in xs) / 1e9:.3f} GB")
+    host = np.zeros(ti, np.uint8)
+    for x, o in zip(xs, in_off):
+        host[o:o + x.nbytes] = x.view(np.uint8)
+    xin = torch.from_numpy(host).cuda()
+    del host
+    xv = [xin[o:o + x.nbytes].view(tdt(x)) for x, o in zip(xs, in_off)]
+    out = torch.zeros(to, dtype=torch.uint8, device="cuda")
+    ov = [out[o:o + b] for o, b in zip(out_off, bounds)]
+    plan = codec.plan_compress(xv, outs=ov, tune=True, graph=True)
+    streams = plan.run()
+    lens = [s.numel() for s in streams]
+    got = out.cpu().numpy()
+    _log(f"[batch-10000] plan {plan.info()['form']}, streams {sum(lens):,} bytes; oracle")
+
+    def check(i):
+        w = orc.compress(xs[i])
+        g = got[out_off[i]:out_off[i] + lens[i]].tobytes()
+        return None if g == w else f"series {i} ({xs[i].size} values, {xs[i].dtype}) differs from the oracle"
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        for err in ex.map(check, range(len(xs))):
+            assert err is None, err
+    yin = torch.zeros_like(xin)
+    yv = [yin[o:o + x.nbytes].view(tdt(x)) for x, o in zip(xs, in_off)]
+    dplan = codec.plan_decompress(streams, [x.size for x in xs], [tdt(x) for x in xs], outs=yv, tune=True,
+                                  graph=True)
+    dplan.run()
+    assert torch.equal(yin, xin), "round trip of the batch"
+    _log("[batch-10000] every series equals the oracle's stream and round-trips")
+    plan.close()
+    dplan.close()
+    del xin, out, yin
+    torch.cuda.empty_cache()
