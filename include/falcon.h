@@ -466,6 +466,19 @@ falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms);
  * decompression: 0, scan, decoding kernel. */
 falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms);
 
+/* The context keeps the events of its last FALCON_TIMED_CALLS timed calls
+ * (falcon_compress, falcon_compress_variant, falcon_decompress,
+ * falcon_decompress_n), so that a caller who enqueues many asynchronous
+ * calls and synchronises once can still read each call's stages. */
+#define FALCON_TIMED_CALLS 64
+
+/* ms[0..2] as falcon_last_stage_ms for the timed call made `back` timed
+ * calls before the last (back = 0: the last one); waits for that call's
+ * work.  FALCON_ERR_INVALID_ARG if back >= FALCON_TIMED_CALLS, or if that
+ * many timed calls have not been made, or that call failed before its
+ * kernels were enqueued. */
+falcon_status falcon_call_stage_ms(falcon_ctx* ctx, unsigned back, float* ms);
+
 /* Static, human-readable name of a status code. */
 const char* falcon_status_str(falcon_status st);
 

@@ -51,6 +51,7 @@ class Opts(ctypes.Structure):
 
 
 OPT_BLOCKING = 1
+TIMED_CALLS = 64  # FALCON_TIMED_CALLS: timed calls whose stage times the context keeps
 OPT_DEVICE_LENGTHS = 2
 FORMS = {"two_pass": 0, "single_pass": 1}
 
@@ -113,6 +114,8 @@ def _load():
     L.falcon_last_kernel_ms.restype = i
     L.falcon_last_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.falcon_last_stage_ms.restype = i
+    L.falcon_call_stage_ms.argtypes = [vp, ctypes.c_uint, ctypes.POINTER(ctypes.c_float)]
+    L.falcon_call_stage_ms.restype = i
     L.falcon_compress_host.argtypes = [vp, vp, sz, i, vp, sz, ctypes.POINTER(sz)]
     L.falcon_compress_host.restype = i
     L.falcon_decompress_host.argtypes = [vp, vp, sz, vp, sz, ctypes.POINTER(sz)]
@@ -230,6 +233,16 @@ class Codec:
         st = lib().falcon_last_stage_ms(self._ctx, ms)
         if st != 0:
             raise FalconError(st, "falcon_last_stage_ms")
+        return [ms[0], ms[1], ms[2]]
+
+    def call_stage_ms(self, back: int) -> list:
+        """falcon_call_stage_ms: the stages of the timed call made `back`
+        timed calls before the last (0 = the last), for callers that enqueue
+        many asynchronous calls and synchronise once."""
+        ms = (ctypes.c_float * 3)()
+        st = lib().falcon_call_stage_ms(self._ctx, back, ms)
+        if st != 0:
+            raise FalconError(st, "falcon_call_stage_ms")
         return [ms[0], ms[1], ms[2]]
 
     def sync(self):

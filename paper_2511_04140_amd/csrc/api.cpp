@@ -110,6 +110,15 @@ falcon_status prepare_queue(Lane& l, uint64_t nchunks, hipStream_t s) {
   return dev_err(launch_fill_u64(l.qctr, (size_t)kQueueGroups * kQueueStride, 0, s));
 }
 
+// Moves the timing ring to a fresh slot for a timed call and returns its
+// four events; the slot counts as complete once the call has recorded all
+// of them.
+static hipEvent_t* begin_timed(falcon_ctx* ctx) {
+  ctx->ev_slot = (ctx->ev_slot + 1) % FALCON_TIMED_CALLS;
+  ctx->ev_ok[ctx->ev_slot] = false;
+  return ctx->ev[ctx->ev_slot];
+}
+
 // Compression, in one of two forms.  Two passes (the default, and the
 // only form of the ablation variants): a size pass, a scan of the chunk
 // sizes into offsets, a write pass that redoes a4-a7 and writes each chunk
@@ -132,8 +141,8 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
   a.total_chunks = nc;
   a.lens = d_len;
   a.relative = 0;
-  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
-  if (timed) ctx->timed = false;
+  hipEvent_t* ev = timed ? begin_timed(ctx) : nullptr;
+  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ev[i], s)) : FALCON_OK; };
   if (variant == 0 && form == FALCON_FORM_SINGLE_PASS) {
     if ((st = mark(0)) != FALCON_OK || (st = prepare_queue(l, nc ? nc : 1, s)) != FALCON_OK) return st;
     const int nw = kCompressWaves;
@@ -172,10 +181,7 @@ falcon_status enqueue_compress(falcon_ctx* ctx, Lane& l, const void* d_in, uint6
     if ((st = launch(2, g2)) != FALCON_OK) return st;
     if ((st = mark(3)) != FALCON_OK) return st;
   }
-  if (timed) {
-    ctx->timed = true;
-    ctx->timed_compress = true;
-  }
+  if (timed) ctx->ev_ok[ctx->ev_slot] = true;
   return FALCON_OK;
 }
 
@@ -190,8 +196,8 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   // count when the host knows it; otherwise the last chunk's check does that)
   const uint32_t lo = dt == FALCON_FLOAT64 ? 11u : 7u;
   const uint32_t hi = (uint32_t)max_chunk_bytes(dt);
-  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ctx->ev[i], s)) : FALCON_OK; };
-  if (timed) ctx->timed = false;
+  hipEvent_t* ev = timed ? begin_timed(ctx) : nullptr;
+  auto mark = [&](int i) { return timed ? dev_err(hipEventRecord(ev[i], s)) : FALCON_OK; };
   if ((st = mark(0)) != FALCON_OK || (st = mark(1)) != FALCON_OK) return st;
   if ((st = dev_err(launch_scan_sizes(reinterpret_cast<const uint32_t*>(d_in + 32), nc, lo, hi,
                                       payload == kPayloadFromHeader ? ~0ull : payload, l.tiles, l.offsets, l.ctl,
@@ -217,10 +223,7 @@ falcon_status enqueue_decompress(falcon_ctx* ctx, Lane& l, const uint8_t* d_in, 
   if ((st = mark(2)) != FALCON_OK) return st;
   if ((st = dev_err(launch_decompress(a, (int)dt, grid, s))) != FALCON_OK) return st;
   if ((st = mark(3)) != FALCON_OK) return st;
-  if (timed) {
-    ctx->timed = true;
-    ctx->timed_compress = false;
-  }
+  if (timed) ctx->ev_ok[ctx->ev_slot] = true;
   if (!copy_error) return FALCON_OK;
   return dev_err(hipMemcpyAsync(l.stage + 32, &l.ctl->error, 4, hipMemcpyDeviceToHost, s));
 }
@@ -317,10 +320,11 @@ falcon_status falcon_create(int device, const falcon_opts* opts, falcon_ctx** ou
   ctx->device = device;
   ctx->opt_flags = flags;
   ctx->compress_form = form;
-  if (lane_init(ctx->main) != FALCON_OK || hipEventCreate(&ctx->ev[0]) != hipSuccess ||
-      hipEventCreate(&ctx->ev[1]) != hipSuccess || hipEventCreate(&ctx->ev[2]) != hipSuccess ||
-      hipEventCreate(&ctx->ev[3]) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) != hipSuccess) {
+  bool ok = lane_init(ctx->main) == FALCON_OK &&
+            hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) == hipSuccess;
+  for (int c = 0; ok && c < FALCON_TIMED_CALLS; ++c)
+    for (int i = 0; ok && i < 4; ++i) ok = hipEventCreate(&ctx->ev[c][i]) == hipSuccess;
+  if (!ok) {
     falcon_destroy(ctx);
     return FALCON_ERR_DEVICE;
   }
@@ -401,8 +405,9 @@ void falcon_destroy(falcon_ctx* ctx) {
   if (ctx->last_stream) (void)hipStreamSynchronize(ctx->last_stream);
   batch_free(ctx->batch);
   lane_free(ctx->main);
-  for (hipEvent_t e : ctx->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& call : ctx->ev)
+    for (hipEvent_t e : call)
+      if (e) (void)hipEventDestroy(e);
   if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
   for (uint64_t* b : ctx->len_blocks) (void)hipFree(b);
   if (ctx->len_host) (void)hipHostFree(ctx->len_host);
@@ -551,18 +556,25 @@ falcon_status falcon_decompress_each(falcon_ctx* ctx, falcon_series* ss, size_t 
   return st != FALCON_OK ? st : sy;
 }
 
-falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms) {
-  if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
-  if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
-  return dev_err(hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[3]));
+falcon_status falcon_call_stage_ms(falcon_ctx* ctx, unsigned back, float* ms) {
+  if (!ctx || !ms || back >= FALCON_TIMED_CALLS) return FALCON_ERR_INVALID_ARG;
+  const int slot = (ctx->ev_slot + FALCON_TIMED_CALLS - (int)back) % FALCON_TIMED_CALLS;
+  if (!ctx->ev_ok[slot]) return FALCON_ERR_INVALID_ARG;
+  hipEvent_t* ev = ctx->ev[slot];
+  if (hipEventSynchronize(ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
+  for (int i = 0; i < 3; ++i)
+    if (hipEventElapsedTime(ms + i, ev[i], ev[i + 1]) != hipSuccess) return FALCON_ERR_DEVICE;
+  return FALCON_OK;
 }
 
-falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms) {
-  if (!ctx || !ms || !ctx->timed) return FALCON_ERR_INVALID_ARG;
-  if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return FALCON_ERR_DEVICE;
-  for (int i = 0; i < 3; ++i)
-    if (hipEventElapsedTime(ms + i, ctx->ev[i], ctx->ev[i + 1]) != hipSuccess) return FALCON_ERR_DEVICE;
-  return FALCON_OK;
+falcon_status falcon_last_stage_ms(falcon_ctx* ctx, float* ms) { return falcon_call_stage_ms(ctx, 0, ms); }
+
+falcon_status falcon_last_kernel_ms(falcon_ctx* ctx, float* ms) {
+  if (!ms) return FALCON_ERR_INVALID_ARG;
+  float st[3];
+  const falcon_status s = falcon_call_stage_ms(ctx, 0, st);
+  if (s == FALCON_OK) *ms = st[0] + st[1] + st[2];
+  return s;
 }
 
 }  // extern "C"

@@ -155,11 +155,13 @@ struct falcon_ctx {
   int grid_q[4][2] = {};
   // the same for the ablation-variant compression kernels: [form][variant][pass]
   int grid_v[3][4][3] = {};
-  // events of the last timed call: before the first kernel, after it, after
-  // the scan, after the last kernel (decompression: the first two coincide)
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool timed = false;
-  bool timed_compress = false;
+  // events of the last FALCON_TIMED_CALLS timed calls, a ring whose slot
+  // ev_slot holds the last call: before the first kernel, after it, after
+  // the scan, after the last kernel (decompression: the first two coincide).
+  // ev_ok marks a slot whose call enqueued all four.
+  hipEvent_t ev[FALCON_TIMED_CALLS][4] = {};
+  bool ev_ok[FALCON_TIMED_CALLS] = {};
+  int ev_slot = 0;
   // host <-> device pipeline
   // defaults measured on MI355X (4 hardware queues per process): 4 streams
   // of 2048-chunk batches beat the 16 x 4096 setting of Sec. 5.1.4 in both

@@ -191,3 +191,47 @@ def test_each_loops_match_the_oracle(orc):
     for x, y in zip(xs, ys):
         assert np.array_equal(y.cpu().numpy().view(np.uint8), x.view(np.uint8))
     c.close()
+
+
+def test_stage_times_of_many_calls(orc):
+    """falcon_call_stage_ms: after several asynchronous compressions and
+    decompressions and one falcon_sync, every call's stage times can be read,
+    newest first (back = 0 is the last call, as falcon_last_stage_ms):
+    compressions have a size pass, a scan and a write pass, decompressions a
+    scan and the decoding kernel.  The ring keeps FALCON_TIMED_CALLS calls;
+    asking beyond it, or for a call never made, is refused."""
+    from paper_2511_04140_amd import codec as C
+    from paper_2511_04140_amd import workloads as W
+    fresh = C.Codec(0, blocking=False)
+    with pytest.raises(C.FalconError):
+        fresh.call_stage_ms(0)
+    fresh.close()
+    c = C.Codec(0, blocking=False)
+    xs = [W.sensor_f64(40 * 1025 + 3, seed=2), W.mixed_f32(30 * 1025 + 5, seed=3, side=32),
+          W.walk_f64(20000, seed=1)]
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    bufs = [torch.zeros(_bound(C, x), dtype=torch.uint8, device="cuda") for x in xs]
+    outs = [torch.empty_like(x) for x in xd]
+    for x, b, o in zip(xd, bufs, outs):
+        c.compress_async(x, b)
+        c.decompress_n_async(b, x.numel(), x.dtype, o)
+    c.sync()
+    n = len(xs)
+    for i in range(n):
+        dec = c.call_stage_ms(2 * (n - 1 - i))
+        comp = c.call_stage_ms(2 * (n - 1 - i) + 1)
+        assert all(v > 0 for v in comp), (i, comp)
+        assert 0 <= dec[0] < 0.05 and dec[1] > 0 and dec[2] > 0, (i, dec)
+        assert torch.equal(outs[i].view(torch.uint8), xd[i].view(torch.uint8))
+    assert c.call_stage_ms(0) == c.last_stage_ms()
+    assert abs(c.last_kernel_ms() - sum(c.last_stage_ms())) < 1e-3
+    with pytest.raises(C.FalconError):
+        c.call_stage_ms(C.TIMED_CALLS)
+    # more calls than the ring holds: the oldest slot still held is readable
+    small = xd[2]
+    for _ in range(C.TIMED_CALLS + 6):
+        c.compress_async(small, bufs[2])
+    c.sync()
+    assert all(v > 0 for v in c.call_stage_ms(C.TIMED_CALLS - 1))
+    assert bufs[2][:32].cpu().numpy().tobytes() == orc.compress(xs[2])[:32]
+    c.close()
