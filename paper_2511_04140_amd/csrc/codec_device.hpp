@@ -112,13 +112,16 @@ __device__ __forceinline__ uint4 gload16(const void* p) {
   const u32x4 v = *gbl(reinterpret_cast<const u32x4*>(p));
   return make_uint4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ void gstore16(void* p, const uint4& v) {
+// The store carries the non-temporal hint: it writes streamed output that
+// no later kernel of the same operation reads, and leaves no dirty lines in
+// the caches for the next kernel to write back.
+__device__ __forceinline__ void gstore16_nt(void* p, const uint4& v) {
   u32x4 w;
   w.x = v.x;
   w.y = v.y;
   w.z = v.z;
   w.w = v.w;
-  *gbl(reinterpret_cast<u32x4*>(p)) = w;
+  __builtin_nontemporal_store(w, gbl(reinterpret_cast<u32x4*>(p)));
 }
 
 __device__ __forceinline__ void load_tables(LdsTables& s) {

@@ -712,7 +712,10 @@ __device__ __forceinline__ void copy_piece(const uint8_t* src, uint8_t* dst, uin
 // a11 (second half): copies a payload assembled in LDS at byte phase ph
 // (buf + ph holds its S bytes, ph = the destination's offset inside its
 // 16-byte block) to dal + ph, dal being 16-byte aligned: whole blocks with
-// one 16-byte LDS read and one 16-byte store each.  The partial first block
+// one 16-byte LDS read and one non-temporal 16-byte store each (a stream is
+// read again, if at all, by a later operation; with ordinary stores its
+// last lines stay dirty in the caches and the next kernel, typically a
+// decompression, pays for their write-back).  The partial first block
 // [ph, 16) and last block [0, end & 15) are each written as at most four
 // naturally aligned pieces (1, 2, 4 and 8 bytes); a payload inside a single
 // block, byte by byte.
@@ -722,7 +725,7 @@ __device__ __forceinline__ void copy_payload(const uint8_t* buf, uint8_t* dal, u
   for (uint32_t k = lane; k < nblk; k += 64) {
     const uint32_t b_lo = 16 * k, b_hi = b_lo + 16;
     if (b_lo >= ph && b_hi <= end) {
-      gstore16(dal + b_lo, *reinterpret_cast<const uint4*>(buf + b_lo));
+      gstore16_nt(dal + b_lo, *reinterpret_cast<const uint4*>(buf + b_lo));
     } else if (b_lo < ph && b_hi <= end) {
       // head: bytes ph .. 15 of the block, pieces in increasing size
       uint32_t o = ph;
@@ -1331,9 +1334,10 @@ __device__ __forceinline__ uint64_t look_back(const CompressArgs& a, uint64_t tg
 // a11 for the single pass: copies a payload assembled at phase 0 (buf holds
 // its S bytes) to dst, which may have any byte phase ph = dst & 15.  Whole
 // 16-byte destination blocks are built from five aligned LDS dwords shifted
-// by the phase (v_alignbyte) and stored with one 16-byte store each; the
-// partial first and last blocks are written byte by byte, one byte per lane
-// (lanes 0-15 the first block, 16-31 the last).
+// by the phase (v_alignbyte) and stored with one non-temporal 16-byte store
+// each (as in copy_payload); the partial first and last blocks are written
+// byte by byte, one byte per lane (lanes 0-15 the first block, 16-31 the
+// last).
 __device__ __forceinline__ void copy_payload_shifted(const uint8_t* buf, uint8_t* dst, uint32_t S, int lane) {
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
   uint8_t* const dal = dst - ph;
@@ -1353,7 +1357,7 @@ __device__ __forceinline__ void copy_payload_shifted(const uint8_t* buf, uint8_t
     v.y = __builtin_amdgcn_alignbyte(w2, w1, r);
     v.z = __builtin_amdgcn_alignbyte(w3, w2, r);
     v.w = __builtin_amdgcn_alignbyte(w4, w3, r);
-    gstore16(dal + 16u * k, v);
+    gstore16_nt(dal + 16u * k, v);
   }
   // partial blocks: the first if ph > 0 (or the payload ends inside it), the
   // last if end is not block aligned and it is not the first
