@@ -520,9 +520,12 @@ __device__ __forceinline__ void transform_front(const LdsTables& sm, uint8_t* bu
   int lane = lane_in;
   asm volatile("" : "+v"(lane));
 
-  // a4: Eq. 3 -> g, written to LDS in skewed natural order
+  // a4: Eq. 3 -> g, written to LDS in skewed natural order.  Element
+  // i = 1 + 64k + L goes to slot i + (i >> 4) = s0 + 68k: one base per lane
+  // and a constant offset per k (an immediate of the LDS store)
   U* g = reinterpret_cast<U*>(buf);
   {
+    const uint32_t s0 = 1u + (uint32_t)lane + ((1u + (uint32_t)lane) >> 4);
     const F P = T::pow10(sm, case1 ? cp.A : 0);
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
@@ -535,8 +538,7 @@ __device__ __forceinline__ void transform_front(const LdsTables& sm, uint8_t* bu
         gk = zigzag<U>(vb[k]);
       }
       if (k < 16) {
-        const uint32_t i = 1 + 64 * k + lane;
-        g[i + (i >> 4)] = gk;
+        g[s0 + 68u * k] = gk;
       } else if (lane == 0) {
         g[0] = gk;
       }
@@ -976,6 +978,9 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
   const bool case1 = uniform((uint32_t)(A <= T::AMAX && B <= T::BMAX)) != 0;
   wave_lds_sync();
   U* vals = reinterpret_cast<U*>(buf);
+  // element 16L + 1 + i sits at slot idx + (idx >> 4) = 17L + 1 + i + ((1 + i) >> 4)
+  const uint32_t b17 = 17u * (uint32_t)lane;
+  auto slot_of = [](int i) { return (uint32_t)(1 + i + ((1 + i) >> 4)); };
   if (case1) {
     // Inverse Eq. 3: v = g / 10^alpha, correctly rounded.  With y the
     // correctly rounded reciprocal of P = 10^alpha and q = RN(g * y), the
@@ -996,17 +1001,11 @@ __device__ __forceinline__ void decompress_chunk(const LdsTables& sm, uint8_t* b
       return T::fma(T::fma(-q, P, g), y, q);
     };
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t idx = 16u * lane + 1 + i;
-      vals[idx + (idx >> 4)] = T::u(quot((F)(S_)(U)(basev + gv[i])));
-    }
+    for (int i = 0; i < 16; ++i) vals[b17 + slot_of(i)] = T::u(quot((F)(S_)(U)(basev + gv[i])));
     if (lane == 0) vals[0] = T::u(quot((F)(S_)z1));
   } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t idx = 16u * lane + 1 + i;
-      vals[idx + (idx >> 4)] = unzigzag<U>((U)(basev + gv[i]));
-    }
+    for (int i = 0; i < 16; ++i) vals[b17 + slot_of(i)] = unzigzag<U>((U)(basev + gv[i]));
     if (lane == 0) vals[0] = unzigzag<U>(z1);
   }
   wave_lds_sync();
