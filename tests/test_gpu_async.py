@@ -221,7 +221,7 @@ def test_stage_times_of_many_calls(orc):
         dec = c.call_stage_ms(2 * (n - 1 - i))
         comp = c.call_stage_ms(2 * (n - 1 - i) + 1)
         assert all(v > 0 for v in comp), (i, comp)
-        assert 0 <= dec[0] < 0.05 and dec[1] > 0 and dec[2] > 0, (i, dec)
+        assert 0 <= dec[0] < 0.5 and dec[1] > 0 and dec[2] > 0, (i, dec)  # stage 0 holds no kernel
         assert torch.equal(outs[i].view(torch.uint8), xd[i].view(torch.uint8))
     assert c.call_stage_ms(0) == c.last_stage_ms()
     assert abs(c.last_kernel_ms() - sum(c.last_stage_ms())) < 1e-3
