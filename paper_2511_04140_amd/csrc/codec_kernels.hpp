@@ -1155,7 +1155,12 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
   assemble_payload<T>(buf + ph, cp, flags, S, lane);
   wave_lds_sync();
+  // the payload's stores go out at a raised wave priority, so that the
+  // SIMD issues them ahead of the other waves' arithmetic and the memory
+  // system has them sooner
+  __builtin_amdgcn_s_setprio(2);
   copy_payload(buf, dst - ph, ph, S, lane);
+  __builtin_amdgcn_s_setprio(0);
   if (c == nc - 1) {
     write_stream_header(sd.out, sd.dtype, sd.n, off + S, lane);
     if (a.lens && lane == 0) a.lens[sd.idx] = kHdrBytes + 4 * nc + off + S;
