@@ -9,9 +9,13 @@ float64 sensor-like values (2 GiB, 65,536-value segments at 1-6 decimal
 places, 1% full-precision outliers, specials at 1e-5), seeded synthetic.
 
 Prints one JSON line.  `value` is the round-trip throughput: original bytes
-per step divided by the step time.  Compress and decompress throughputs
-(the paper's CT and DT, here device-resident) and the compression ratio are
-reported beside it.
+per step divided by the step time.  The timed steps are asynchronous calls
+on one stream (falcon_compress, then falcon_decompress_n with the count and
+dtype just compressed) with one wait at the end of the region; every
+kernel's duration comes from the HIP events the library records for each
+call, read afterwards (falcon_call_stage_ms).  Compress and decompress
+throughputs (the paper's CT and DT, here device-resident) and the
+compression ratio are reported beside it.
 """
 import argparse
 import hashlib
