@@ -1153,12 +1153,12 @@ __device__ __forceinline__ void write_chunk(const LdsTables& tab, uint8_t* buf, 
   // the copy moves whole aligned blocks
   uint8_t* dst = sd.out + kHdrBytes + 4 * nc + off;
   const uint32_t ph = uniform((uint32_t)((uintptr_t)dst & 15u));
+  // the payload's assembly and stores run at a raised wave priority: the
+  // SIMD issues this wave's LDS writes and stores ahead of the other waves'
+  // arithmetic, so that the payload reaches the memory system sooner
+  __builtin_amdgcn_s_setprio(2);
   assemble_payload<T>(buf + ph, cp, flags, S, lane);
   wave_lds_sync();
-  // the payload's stores go out at a raised wave priority, so that the
-  // SIMD issues them ahead of the other waves' arithmetic and the memory
-  // system has them sooner
-  __builtin_amdgcn_s_setprio(2);
   copy_payload(buf, dst - ph, ph, S, lane);
   __builtin_amdgcn_s_setprio(0);
   if (c == nc - 1) {
